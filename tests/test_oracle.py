@@ -1,0 +1,405 @@
+"""Pins for the FP64 oracle (CPU only).
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/paper_values.txt), closed forms of small windows,
+invariants of the method, the textbook symmetric biweight, and a brute-force
+restatement on tiny inputs (tests/bruteforce.py).  Section references are to
+arXiv 2604.06602.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
+SCALE = 0.6745
+
+
+def paper_values():
+    out = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, val, tol, _cite = [p.strip() for p in line.split("|", 3)]
+            out[name] = (val, float(tol))
+    return out
+
+
+PV = paper_values()
+
+
+def pv(name):
+    val, tol = PV[name]
+    return float(val), tol
+
+
+# --------------------------------------------------------------------------
+# Window rule, Section 2 and Section 4.4
+
+
+def test_window_rule_matches_paper(oracle_lib):
+    w_tess, _ = pv("window_tess_2min")
+    w_kep, _ = pv("window_kepler_30min")
+    assert oracle_lib.window_from_cadence(2 / 1440) == w_tess
+    assert oracle_lib.window_from_cadence(30 / 1440) == w_kep
+    assert oracle_lib.window_from_cadence(29.4 / 1440) == w_kep
+    days, tol = pv("window_tess_days")
+    assert abs(w_tess * 2 / 1440 - days) <= tol
+
+
+def test_window_rule_is_odd_and_rejects_bad(oracle_lib):
+    for cad_min in [0.5, 1, 2, 10, 20, 29.4, 30, 60, 120]:
+        W = oracle_lib.window_from_cadence(cad_min / 1440)
+        assert W % 2 == 1
+        assert abs(W - 0.5 / (cad_min / 1440)) <= 1.5
+    assert oracle_lib.window_from_cadence(0.0) == -1
+    assert oracle_lib.window_from_cadence(-1.0) == -1
+
+
+# --------------------------------------------------------------------------
+# Weight function, Section 2.3 Eqs. 2-3
+
+
+def test_weight_paper_values(oracle_lib):
+    v1, t1 = pv("weight_u-0.3_alpha1")
+    v2, t2 = pv("weight_u-0.3_alpha2")
+    assert abs(oracle_lib.weight(-0.3, 1.0) - v1) <= t1
+    assert abs(oracle_lib.weight(-0.3, 2.0) - v2) <= t2
+    # upward deviations keep their natural scale (Section 1, item 1)
+    assert abs(oracle_lib.weight(0.3, 2.0) - v1) <= t1
+
+
+def test_weight_scale_convention_matches_section_2_5(oracle_lib):
+    """A 1-sigma dip, with s = 0.6745 sigma and c = 5, lands at u ~ -0.3 and
+    gets the weights Section 2.5 quotes; other scale conventions do not."""
+    c, _ = pv("default_c")
+    k, _ = pv("scale_constant")
+    u = -1.0 / (c * k)
+    v1, t1 = pv("weight_dz1_alpha1")
+    v2, t2 = pv("weight_dz1_alpha2")
+    assert abs(oracle_lib.weight(u, 1.0) - v1) <= t1
+    assert abs(oracle_lib.weight(u, 2.0) - v2) <= t2
+    # s = sigma / 0.6745 would put the dip at u ~ -0.135: far from 0.41
+    assert abs(oracle_lib.weight(-k / c, 2.0) - v2) > 0.3
+
+
+def test_weight_support_and_shape(oracle_lib):
+    assert oracle_lib.weight(0.0, 2.0) == 1.0
+    assert oracle_lib.weight(1.0, 2.0) == 0.0      # |u_eff| < 1 is strict
+    assert oracle_lib.weight(-0.5, 2.0) == 0.0     # alpha*u = -1
+    assert oracle_lib.weight(-0.49, 2.0) > 0.0
+    assert oracle_lib.weight(0.99, 2.0) > 0.0
+    assert oracle_lib.weight(5.0, 1.0) == 0.0
+    # alpha = 1 is symmetric (Section 2.3)
+    for u in np.linspace(-1.2, 1.2, 49):
+        assert oracle_lib.weight(u, 1.0) == oracle_lib.weight(-u, 1.0)
+    # monotone non-increasing in |u_eff| on each side
+    ws = [oracle_lib.weight(u, 2.0) for u in np.linspace(0, 1.1, 40)]
+    assert all(a >= b for a, b in zip(ws, ws[1:]))
+
+
+# --------------------------------------------------------------------------
+# Median, Section 2.1
+
+
+def _f32s(xs):
+    return np.array(xs, dtype=np.float32)
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.lists(st.sampled_from([-2.0, -1.0, -0.0, 0.0, 0.5, 1.0, 1.5, 3.0, 1e-30, -1e-30,
+                                 float("inf"), float("-inf")]), min_size=1, max_size=12))
+def test_median_bruteforce_ties_and_zeros(oracle_lib, xs):
+    x = _f32s(xs)
+    got = oracle_lib.median(x)
+    want = bf.rank_median([float(v) for v in x])
+    assert bf.bits(float(got)) == bf.bits(want)
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.lists(st.floats(width=32, allow_nan=False), min_size=1, max_size=12))
+def test_median_bruteforce_random(oracle_lib, xs):
+    x = _f32s(xs)
+    got = oracle_lib.median(x)
+    want = bf.rank_median([float(v) for v in x])
+    assert bf.bits(float(got)) == bf.bits(want)
+
+
+def test_median_lower_for_even_and_matches_partition(oracle_lib):
+    assert oracle_lib.median([0.0, 1.0]) == 0.0
+    assert oracle_lib.median([4.0, 1.0, 3.0, 2.0]) == 2.0
+    rng = np.random.default_rng(7)
+    for n in [1, 2, 3, 24, 25, 360, 361, 721]:
+        x = rng.normal(1.0, 1e-3, n).astype(np.float32)
+        k = (n - 1) // 2
+        assert oracle_lib.median(x) == np.partition(x, k)[k]
+
+
+def test_negative_zero_orders_below_positive_zero(oracle_lib):
+    assert bf.bits(float(oracle_lib.median([0.0, -0.0]))) == bf.bits(-0.0)
+    assert bf.bits(float(oracle_lib.median([-0.0, 0.0, 0.0]))) == bf.bits(0.0)
+
+
+# --------------------------------------------------------------------------
+# Upper-RMS scale, Section 2.2 Eq. 1
+
+
+def test_upper_scale_hand_examples(oracle_lib):
+    # {1..5}, m=3: points above are 4, 5 -> sigma = sqrt((1+4)/2)
+    assert oracle_lib.upper_scale([1, 2, 3, 4, 5], 3.0) == pytest.approx(SCALE * math.sqrt(2.5), rel=1e-15)
+    # ties with the median are not "above" (strict): only 1 and 10 count
+    assert oracle_lib.upper_scale([0, 0, 0, 1, 10], 0.0) == pytest.approx(SCALE * math.sqrt(101 / 2), rel=1e-15)
+    # nothing above the median: the scale is 0
+    assert oracle_lib.upper_scale([1, 1, 1, 1, 1], 1.0) == 0.0
+    assert oracle_lib.upper_scale([0, 1], 0.0) == pytest.approx(SCALE, rel=1e-15)
+    _, m, s = oracle_lib.window([2.0, 7.0, 2.0, 9.0, 1.0])
+    assert m == 2.0 and s == pytest.approx(SCALE * math.sqrt((25 + 49) / 2), rel=1e-15)
+
+
+def test_upper_scale_dip_immunity(oracle_lib):
+    """Section 2.2: dips below the median never enter the scale."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        x = rng.normal(1.0, 1e-3, 361).astype(np.float32)
+        _, m, s = oracle_lib.window(x)
+        below = np.where(x < m)[0]
+        y = x.copy()
+        y[below[: len(below) // 2]] -= np.float32(0.05)
+        _, m2, s2 = oracle_lib.window(y)
+        assert m2 == m and s2 == s
+
+
+# --------------------------------------------------------------------------
+# Whole-window estimate, Sections 2.1-2.3
+
+
+def textbook_biweight(x, m, s, c, iters):
+    """Symmetric Tukey biweight location about m with a given scale,
+    vectorised: mu <- sum(w x)/sum(w), w = (1 - (r/(c s))^2)^2 on |r| < c s."""
+    x = np.asarray(x, np.float64)
+    mu = float(m)
+    for _ in range(iters):
+        z = (x - mu) / (c * s)
+        w = np.where(np.abs(z) < 1, (1 - z * z) ** 2, 0.0)
+        if w.sum() == 0:
+            break
+        mu = float(np.dot(w, x) / w.sum())
+    return mu
+
+
+def test_alpha_one_is_textbook_biweight(oracle_lib):
+    rng = np.random.default_rng(3)
+    for n in [5, 25, 121, 361]:
+        for _ in range(10):
+            x = (1 + rng.normal(0, 1e-3, n) - 5e-3 * (rng.random(n) < 0.1)).astype(np.float32)
+            t, m, s = oracle_lib.window(x, alpha=1.0, c=5.0, iters=5)
+            assert t == pytest.approx(textbook_biweight(x, m, s, 5.0, 5), rel=1e-13, abs=1e-15)
+
+
+def test_symmetric_data_symmetric_weights(oracle_lib):
+    t, m, _ = oracle_lib.window([1, 2, 3, 4, 5], alpha=1.0)
+    assert m == 3.0 and t == pytest.approx(3.0, abs=1e-14)
+
+
+def test_asymmetry_moves_estimate_up(oracle_lib):
+    """alpha > 1 down-weights points below the location, so the estimate of
+    symmetric data rises above the centre (Sections 2.3 and 4.1)."""
+    t2, _, _ = oracle_lib.window([1, 2, 3, 4, 5], alpha=2.0)
+    t10, _, _ = oracle_lib.window([1, 2, 3, 4, 5], alpha=10.0, c=2.5)
+    assert 3.0 < t2 < 5.0
+    assert t2 < t10 <= 5.0
+
+
+def test_two_point_window_closed_form(oracle_lib):
+    """Window {0, 1}: lower median 0; one point above, so s = 0.6745; after one
+    iteration mu = w/(1+w) with w = (1 - (1/(5*0.6745))^2)^2 (x = 0 sits at
+    u = 0 and has weight 1)."""
+    t1, m, s = oracle_lib.window([0.0, 1.0], alpha=2.0, c=5.0, iters=1)
+    assert m == 0.0 and s == pytest.approx(SCALE, rel=1e-15)
+    w = (1 - (1 / (5 * SCALE)) ** 2) ** 2
+    assert t1 == pytest.approx(w / (1 + w), rel=1e-14)
+
+
+def test_constant_returns_itself(oracle_lib):
+    for v in [1.0, 0.0, -3.5, 1e-20, 7e5]:
+        for n in [1, 2, 25, 361]:
+            t, m, s = oracle_lib.window(np.full(n, v, np.float32))
+            assert s == 0.0 and t == np.float32(v) and m == np.float32(v)
+
+
+def test_iters_zero_gives_median(oracle_lib):
+    rng = np.random.default_rng(5)
+    x = rng.normal(1, 1e-3, 361).astype(np.float32)
+    t, m, _ = oracle_lib.window(x, iters=0)
+    assert t == float(m)
+
+
+def test_estimate_within_window_range(oracle_lib):
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        n = int(rng.integers(1, 400))
+        x = (rng.standard_t(2, n) * 1e-3 + 1).astype(np.float32)
+        for a, c in [(2, 5), (1, 5), (3, 5), (10, 2.5)]:
+            t, _, _ = oracle_lib.window(x, alpha=a, c=c)
+            assert float(x.min()) <= t <= float(x.max())
+
+
+def test_fixed_point_of_the_m_estimator(oracle_lib):
+    """Iterated to convergence, Eq. 4 satisfies sum_i w_i (x_i - mu) = 0 with
+    the weights of Eqs. 2-3 evaluated at the final mu."""
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        x = (1 + rng.normal(0, 1e-3, 361)).astype(np.float64).astype(np.float32)
+        t, m, s = oracle_lib.window(x, alpha=2.0, c=5.0, iters=400)
+        r = x.astype(np.float64) - t
+        w = np.array([oracle_lib.weight(v, 2.0) for v in r / (5.0 * s)])
+        assert abs(np.dot(w, r)) <= 1e-12 * w.sum()
+
+
+def test_power_of_two_scaling_is_bit_exact(oracle_lib):
+    """Every FP64 step commutes with scaling by 2^k (absent under/overflow)."""
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        x = (1 + rng.normal(0, 1e-3, 361) - 2e-3 * (rng.random(361) < 0.05)).astype(np.float32)
+        t, m, s = oracle_lib.window(x)
+        for k in [-3, 1, 5]:
+            t2, m2, s2 = oracle_lib.window(x * np.float32(2.0 ** k))
+            assert t2 == t * 2.0 ** k and m2 == m * np.float32(2.0 ** k) and s2 == s * 2.0 ** k
+
+
+def test_affine_equivariance(oracle_lib):
+    """trend(a x + b) = a trend(x) + b for a > 0 (inputs rounded to float32)."""
+    rng = np.random.default_rng(10)
+    for _ in range(10):
+        x64 = 1 + rng.normal(0, 1e-3, 361)
+        x = x64.astype(np.float32)
+        t, m, s = oracle_lib.window(x)
+        for a, b in [(3.0, 0.25), (0.7, -0.5)]:
+            y = (a * x.astype(np.float64) + b).astype(np.float32)
+            t2, _, s2 = oracle_lib.window(y)
+            # the float32 rounding of y perturbs each value by <= 2^-24 |y|
+            assert abs(t2 - (a * t + b)) <= 4 * 2.0 ** -24 * abs(y).max()
+            assert s2 == pytest.approx(a * s, rel=2e-3)
+
+
+def test_paper_bias_direction_white_noise(oracle_lib):
+    """Sections 2.4 and 4.1: on flat white-noise stars the alpha=2 trend sits
+    above the true level by a fraction of sigma, larger for the aggressive
+    setting, and alpha=1 is nearly unbiased."""
+    rng = np.random.default_rng(12)
+    sigma = 1e-3
+    flux = (1 + rng.normal(0, sigma, 20000)).astype(np.float32)
+    idx = np.arange(400, 19600, 25)
+    out = {}
+    for a, c in [(1.0, 5.0), (2.0, 5.0), (10.0, 2.5)]:
+        tr, _ = oracle_lib.detrend_at(flux, None, 361, idx, alpha=a, c=c)
+        out[a] = (np.mean(tr) - 1.0) / sigma
+    assert abs(out[1.0]) < 0.05
+    assert 0.2 < out[2.0] < 0.7
+    assert out[10.0] > 2.5 * out[2.0]
+
+
+# --------------------------------------------------------------------------
+# Curves: segments, gaps, edges (readings R1-R4) against the brute force
+
+
+def _tiny_cases():
+    rng = np.random.default_rng(21)
+    cases = []
+    for trial in range(40):
+        n = int(rng.integers(0, 60))
+        W = int(rng.choice([1, 3, 5, 7, 9, 11, 25]))
+        flux = (1 + rng.normal(0, 1e-3, n)).astype(np.float32)
+        if n:
+            flux[rng.random(n) < 0.15] = np.nan
+            if rng.random() < 0.2:
+                flux[rng.integers(0, n)] = np.float32(1.0)
+        dt = 2 / 1440
+        time = np.arange(n) * dt
+        if n > 10 and rng.random() < 0.6:
+            cut = int(rng.integers(1, n))
+            time[cut:] += rng.choice([0.3, 0.6, 2.0])
+        if n and rng.random() < 0.2:
+            time[rng.integers(0, n)] = np.nan
+        cases.append((flux, time if trial % 5 else None, W))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_detrend_matches_bruteforce(oracle_lib, case):
+    flux, time, W = _tiny_cases()[case]
+    for a, c, it in [(2.0, 5.0, 5), (1.0, 5.0, 3), (10.0, 2.5, 5)]:
+        tr, md = oracle_lib.detrend(flux, time, W, a, c, it)
+        btr, bmd = bf.detrend(flux, time, W, a, c, it)
+        btr = np.array(btr)
+        bmd = np.array(bmd, dtype=np.float32)
+        assert np.array_equal(np.isnan(tr), np.isnan(btr))
+        ok = ~np.isnan(btr)
+        assert np.array_equal(md[ok].view(np.uint32), bmd[ok].view(np.uint32))
+        np.testing.assert_allclose(tr[ok], btr[ok], rtol=1e-12, atol=1e-15)
+
+
+def test_segment_rules(oracle_lib):
+    dt = 2 / 1440
+    n = 100
+    t = np.arange(n) * dt
+    t[50:] += 0.5            # gap of 0.5 + dt > 0.5 days: a break
+    f = np.ones(n, np.float32)
+    f[10] = np.nan
+    lo, hi = oracle_lib.segments(f, t, 9)
+    assert lo[0] == 0 and hi[0] == 49 and lo[10] == -1 and lo[60] == 50 and hi[60] == 99
+    t2 = np.arange(n) * dt
+    t2[50:] += 0.5 - dt - 1e-9  # a step of just under 0.5 days: no break
+    lo, hi = oracle_lib.segments(f, t2, 9)
+    assert lo[60] == 0 and hi[60] == 99
+    # minimum segment length floor(W/3): 7 valid samples live at W=21, dead at W=25
+    g = np.full(30, np.nan, np.float32)
+    g[5:12] = 1.0
+    assert (oracle_lib.segments(g, None, 21)[0][5:12] == 5).all()
+    assert (oracle_lib.segments(g, None, 25)[0][5:12] == -1).all()
+
+
+def test_w1_returns_flux(oracle_lib):
+    rng = np.random.default_rng(4)
+    f = rng.normal(1, 1e-3, 500).astype(np.float32)
+    f[::17] = np.nan
+    tr, md = oracle_lib.detrend(f, None, 1)
+    ok = ~np.isnan(f)
+    assert np.array_equal(md[ok], f[ok]) and np.array_equal(tr[ok], f[ok].astype(np.float64))
+    assert np.isnan(tr[~ok]).all()
+
+
+def test_detrend_at_and_batch_agree_with_detrend(oracle_lib):
+    import synth
+    b = synth.config_batch(3, n_curves=4)
+    # shorten the curves to keep this quick
+    curves = [b.curve(i) for i in range(b.n_curves)]
+    curves = [(f[:3000], t[:3000], W) for f, t, W in curves]
+    packed = synth.lightcurves.pack(curves)
+    tr, md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W, n_threads=3)
+    off = packed.offsets
+    for i, (f, t, W) in enumerate(curves):
+        t1, m1 = oracle_lib.detrend(f, t, W)
+        sl = slice(off[i], off[i] + f.size)
+        assert np.array_equal(t1, tr[sl], equal_nan=True)
+        assert np.array_equal(m1.view(np.uint32), md[sl].view(np.uint32))
+        idx = np.array([0, 1, 17, f.size // 2, f.size - 1])
+        t2, m2 = oracle_lib.detrend_at(f, t, W, idx)
+        assert np.array_equal(t2, t1[idx], equal_nan=True)
+
+
+def test_bad_arguments_rejected(oracle_lib):
+    f = np.ones(10, np.float32)
+    for W, a, c, it in [(4, 2, 5, 5), (0, 2, 5, 5), (5, 0, 5, 5), (5, 2, -1, 5),
+                        (5, 2, 5, -1), (5, float("nan"), 5, 5)]:
+        with pytest.raises(ValueError):
+            oracle_lib.detrend(f, None, W, a, c, it)
