@@ -1,0 +1,150 @@
+/*
+ * umi.h -- C ABI of the MI355X (gfx950) UMI detrending library.
+ *
+ * UMI (arXiv 2604.06602, Section 2) computes, at every sample of a light
+ * curve, a robust location estimate over a window of W samples centred on it:
+ *   Phase 1 (Section 2.1)        the exact window median;
+ *   Phase 2 (Section 2.2, Eq. 1) the upper-RMS scale s = 0.6745 * sigma_upper
+ *                                from the points strictly above the median;
+ *   Phase 3 (Section 2.3, Eqs. 2-4) `iters` asymmetric Tukey-bisquare
+ *                                re-weightings with residuals below the
+ *                                location scaled by alpha, u = (x - mu)/(c s).
+ * The estimate is the "trend"; Section 2 also fixes W = round(0.5/dt) | 1.
+ *
+ * Conventions fixed by this library (where the paper is silent):
+ *   - the window is the sample-index window [i-h, i+h], h = (W-1)/2, cut at the
+ *     ends of the sample's segment; invalid samples inside it are skipped;
+ *   - a sample is valid when its flux is finite and, if a time array is given,
+ *     its time is finite;
+ *   - a new segment starts where consecutive valid times differ by more than
+ *     UMI_GAP_DAYS (strictly); with no time array there are no breaks;
+ *   - a segment with fewer than max(1, floor(W/3)) valid samples (the minimum
+ *     segment length scaled to W/3, Section 4.4) gives NaN;
+ *   - the median is the lower median (0-based rank floor((n-1)/2)) in IEEE-754
+ *     totalOrder of the float32 bits, returned bit-exact;
+ *   - if no point lies strictly above the median the scale is 0 and the trend
+ *     is the median; iters = 0 returns the median.
+ * Arithmetic is float32 on the GPU.
+ *
+ * Memory and streams.  Every array argument is a DEVICE pointer owned by the
+ * caller unless marked [host].  Calls are asynchronous on `stream` (a
+ * hipStream_t, NULL = the legacy default stream): they validate on the host,
+ * enqueue work and return without synchronising.  The caller keeps every
+ * buffer alive until that stream work completes.  The library keeps a
+ * workspace per (device, stream), grown on demand and freed by umi_release();
+ * it retains no caller pointer after a call returns.
+ *
+ * Packed ragged batches.  Curve b occupies samples [off_b, off_b + lengths[b])
+ * of every per-sample array, where off is the exclusive prefix sum of lengths.
+ *
+ * Errors.  Functions return a umi_status and never throw.  Arguments are
+ * checked before anything is enqueued; on UMI_ERR_INVALID_ARG and
+ * UMI_ERR_UNSUPPORTED nothing is written.  umi_last_error() returns a
+ * thread-local message for the last failing call on the calling thread.
+ * NaN outputs at invalid samples or dead segments are data, not errors.
+ */
+#ifndef UMI_H
+#define UMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UMI_GAP_DAYS 0.5     /* segment break threshold in days */
+#define UMI_MAX_WINDOW 2047  /* largest supported W */
+
+typedef enum {
+    UMI_OK = 0,
+    UMI_ERR_INVALID_ARG = 1, /* bad argument; nothing enqueued */
+    UMI_ERR_NO_MEMORY = 2,   /* workspace could not be allocated */
+    UMI_ERR_DEVICE = 3,      /* a HIP runtime or launch error */
+    UMI_ERR_UNSUPPORTED = 4  /* valid but outside this build's limits (W) */
+} umi_status;
+
+/* Launch modes of the batch call. */
+typedef enum {
+    UMI_MODE_PERSISTENT = 0, /* one launch for the whole batch: a grid of
+                                long-lived workgroups pops cost-sorted tiles
+                                from a device work queue (default) */
+    UMI_MODE_PER_CURVE = 1   /* one launch per curve (comparison mode) */
+} umi_mode;
+
+/* Tuning knobs; zero in a field means "use the library's choice" (its
+ * built-in defaults, or the tuning table loaded with umi_set_tuning). */
+typedef struct {
+    int32_t mode;          /* umi_mode */
+    int32_t tile;          /* output positions per tile (0 = auto) */
+    int32_t groups_per_cu; /* persistent workgroups per compute unit (0 = auto) */
+    int32_t reserved;      /* must be 0 */
+    void* main_start;      /* optional hipEvent_t recorded on the stream just
+                              before the main (estimate) kernel(s) */
+    void* main_stop;       /* optional hipEvent_t recorded just after them */
+} umi_launch;
+
+/*
+ * umi_detrend -- one curve (Section 2; gap handling per Section 4.4).
+ *   flux   [n] float32 fluxes.
+ *   time   [n] float64 times in days, or NULL for no gap breaks.
+ *   n      number of samples (>= 0; 0 is a no-op).
+ *   W      window in samples: odd, 1 <= W <= UMI_MAX_WINDOW.
+ *   alpha  asymmetry factor for residuals below the location (> 0, finite);
+ *          2 is the paper's default, 1 the symmetric biweight.
+ *   c      bisquare tuning constant (> 0, finite); the paper uses 5.
+ *   iters  number of re-weighting iterations (>= 0); the paper uses 5.
+ *   trend  [n] float32 out: the location estimate, NaN at invalid samples and
+ *          in dead segments.
+ *   median [n] float32 out (may be NULL): the window median, bit-exact.
+ *   stream hipStream_t to enqueue on.
+ * Same as umi_detrend_batch with one curve.
+ */
+umi_status umi_detrend(const float* flux, const double* time, int64_t n,
+                       int32_t W, float alpha, float c, int32_t iters,
+                       float* trend, float* median, void* stream);
+
+/*
+ * umi_detrend_batch -- a packed ragged batch of curves in one call.
+ *   flux, time, trend, median  as for umi_detrend, over sum(lengths) samples.
+ *   lengths  [host] n_curves sample counts (>= 0).
+ *   n_curves number of curves (>= 0; 0 is a no-op).
+ *   W        [host] n_curves odd window sizes, one per curve.
+ *   alpha, c, iters  as for umi_detrend, shared by all curves.
+ *   launch   [host] launch options, or NULL for the defaults.
+ * The call copies the tile list it builds to the device from a pinned
+ * staging buffer; `lengths` and `W` may be reused as soon as it returns.
+ */
+umi_status umi_detrend_batch(const float* flux, const double* time,
+                             const int64_t* lengths, int64_t n_curves,
+                             const int32_t* W, float alpha, float c,
+                             int32_t iters, float* trend, float* median,
+                             const umi_launch* launch, void* stream);
+
+/* Window-size rule of Section 2: round(window_days / cadence_days) | 1.
+ * Returns -1 when either argument is not positive and finite. */
+int32_t umi_window_from_cadence(double cadence_days, double window_days);
+
+/* Tuning table: text lines "W_max tile groups_per_cu", sorted by W_max; a
+ * batch curve uses the first line with W <= W_max.  NULL restores the
+ * built-in defaults.  Returns UMI_ERR_INVALID_ARG on a malformed table. */
+umi_status umi_set_tuning(const char* table_text);
+
+/* Thread-local message for the last non-OK status on this thread. */
+const char* umi_last_error(void);
+
+/* Waits for this library's outstanding work and frees every cached
+ * workspace.  Call only when no other thread is inside the library. */
+void umi_release(void);
+
+/* Library version string. */
+const char* umi_version(void);
+
+/* Test hook: the next call on this thread returns `s` without enqueuing
+ * anything (UMI_OK disarms it).  Used to exercise error propagation. */
+void umi_debug_inject_error(umi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UMI_H */

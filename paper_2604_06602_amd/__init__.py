@@ -1,0 +1,24 @@
+"""UMI sliding-window asymmetric robust detrending on MI355X (gfx950).
+
+The estimate of arXiv 2604.06602 (Section 2) -- window median, upper-RMS
+scale, asymmetric Tukey-bisquare iterations -- at every sample of every light
+curve, computed by hand-written HIP kernels behind a small C ABI
+(include/umi.h).  This package is the thin Python binding over that library
+plus the batching helpers and the serving loop built on it.
+"""
+from ._lib import (  # noqa: F401
+    MAX_WINDOW,
+    MODE_PER_CURVE,
+    MODE_PERSISTENT,
+    LaunchOptions,
+    UmiError,
+    debug_inject_error,
+    detrend,
+    detrend_batch,
+    detrend_batch_into,
+    last_error,
+    release,
+    set_tuning,
+    version,
+    window_from_cadence,
+)

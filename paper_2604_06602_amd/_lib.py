@@ -1,0 +1,195 @@
+"""ctypes binding over libumi.so (include/umi.h).
+
+Argument marshalling only: every step of the estimate runs in the HIP
+kernels.  torch supplies device memory and the current HIP stream.  If the
+library has not been built, importing this module raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libumi.so")
+
+UMI_OK = 0
+UMI_ERR_INVALID_ARG = 1
+UMI_ERR_NO_MEMORY = 2
+UMI_ERR_DEVICE = 3
+UMI_ERR_UNSUPPORTED = 4
+STATUS_NAMES = {0: "UMI_OK", 1: "UMI_ERR_INVALID_ARG", 2: "UMI_ERR_NO_MEMORY",
+                3: "UMI_ERR_DEVICE", 4: "UMI_ERR_UNSUPPORTED"}
+MODE_PERSISTENT = 0
+MODE_PER_CURVE = 1
+MAX_WINDOW = 2047
+
+
+class UmiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("main_start", ctypes.c_void_p), ("main_stop", ctypes.c_void_p)]
+
+
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libumi.so is not built (%s); run `python -m paper_2604_06602_amd.build` "
+                          "or __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.umi_detrend.restype = ctypes.c_int
+    lib.umi_detrend.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_int32, _vp, _vp, _vp]
+    lib.umi_detrend_batch.restype = ctypes.c_int
+    lib.umi_detrend_batch.argtypes = [_vp, _vp, _i64p, ctypes.c_int64, _i32p, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_int32, _vp, _vp,
+                                      ctypes.POINTER(Launch), _vp]
+    lib.umi_window_from_cadence.restype = ctypes.c_int32
+    lib.umi_window_from_cadence.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.umi_set_tuning.restype = ctypes.c_int
+    lib.umi_set_tuning.argtypes = [ctypes.c_char_p]
+    lib.umi_last_error.restype = ctypes.c_char_p
+    lib.umi_last_error.argtypes = []
+    lib.umi_release.restype = None
+    lib.umi_release.argtypes = []
+    lib.umi_version.restype = ctypes.c_char_p
+    lib.umi_version.argtypes = []
+    lib.umi_debug_inject_error.restype = None
+    lib.umi_debug_inject_error.argtypes = [ctypes.c_int]
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != UMI_OK:
+        raise UmiError(status, lib.umi_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return lib.umi_last_error().decode(errors="replace")
+
+
+def version() -> str:
+    return lib.umi_version().decode()
+
+
+def window_from_cadence(cadence_days: float, window_days: float = 0.5) -> int:
+    """Window-size rule of Section 2: round(window / cadence) | 1 (-1 if invalid)."""
+    return int(lib.umi_window_from_cadence(float(cadence_days), float(window_days)))
+
+
+def set_tuning(table_text: str | None):
+    _check(lib.umi_set_tuning(None if table_text is None else table_text.encode()))
+
+
+def release():
+    lib.umi_release()
+
+
+def debug_inject_error(status: int):
+    lib.umi_debug_inject_error(int(status))
+
+
+# ---------------------------------------------------------------------------
+# tensor-facing calls
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_ptr(t, dtype, name, n):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class LaunchOptions:
+    mode: int = MODE_PERSISTENT
+    tile: int = 0
+    groups_per_cu: int = 0
+    main_start: object = None  # torch.cuda.Event recorded before the main kernel
+    main_stop: object = None   # torch.cuda.Event recorded after it
+
+    def as_struct(self) -> Launch:
+        def ev(e):
+            return None if e is None else ctypes.c_void_p(int(e.cuda_event))
+        return Launch(int(self.mode), int(self.tile), int(self.groups_per_cu), 0,
+                      ev(self.main_start), ev(self.main_stop))
+
+
+def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=5.0, iters=5,
+                       launch: LaunchOptions | None = None, stream=None):
+    """Raw batch call on preallocated device tensors (packed ragged layout)."""
+    torch = _torch()
+    lengths = np.ascontiguousarray(lengths, dtype=np.int64)
+    Wa = np.ascontiguousarray(np.broadcast_to(np.asarray(W, dtype=np.int32), lengths.shape))
+    n = int(lengths.sum()) if lengths.size else 0
+    fp = _dev_ptr(flux, torch.float32, "flux", n)
+    tp = _dev_ptr(time, torch.float64, "time", n)
+    op = _dev_ptr(trend, torch.float32, "trend", n)
+    mp = _dev_ptr(median, torch.float32, "median", n)
+    lp = None
+    if launch is not None:
+        lp = ctypes.byref(launch.as_struct())
+    st = lib.umi_detrend_batch(fp, tp, lengths.ctypes.data_as(_i64p), lengths.size,
+                               Wa.ctypes.data_as(_i32p), float(alpha), float(c), int(iters),
+                               op, mp, lp, _stream_handle(stream))
+    _check(st)
+
+
+def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, with_median=False,
+                  launch: LaunchOptions | None = None, stream=None):
+    """Packed ragged batch: returns (trend, median or None) as device tensors."""
+    torch = _torch()
+    trend = torch.empty_like(flux)
+    median = torch.empty_like(flux) if with_median else None
+    detrend_batch_into(flux, time, lengths, W, trend, median, alpha, c, iters, launch, stream)
+    return trend, median
+
+
+def detrend(flux, time=None, W=361, alpha=2.0, c=5.0, iters=5, with_median=False, stream=None):
+    """One curve: returns (trend, median or None) as device tensors."""
+    torch = _torch()
+    n = flux.numel()
+    trend = torch.empty_like(flux)
+    median = torch.empty_like(flux) if with_median else None
+    st = lib.umi_detrend(_dev_ptr(flux, torch.float32, "flux", n),
+                         _dev_ptr(time, torch.float64, "time", n), n, int(W), float(alpha),
+                         float(c), int(iters), _dev_ptr(trend, torch.float32, "trend", n),
+                         _dev_ptr(median, torch.float32, "median", n), _stream_handle(stream))
+    _check(st)
+    return trend, median

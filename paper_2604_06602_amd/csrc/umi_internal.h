@@ -1,0 +1,38 @@
+// Internal layout shared by the host launcher and the HIP kernels of the UMI
+// library.  Nothing here is part of the public C ABI (include/umi.h).
+#pragma once
+
+#include <stdint.h>
+
+namespace umi {
+
+// Largest staged tile: output positions plus the W-1 halo.  The tile sort and
+// the wavelet matrix work on power-of-two padded sizes up to this.
+constexpr int kStageMax = 2048;
+constexpr int kStageLog2 = 11;
+constexpr int kWords = kStageMax / 64 + 1;  // bit-vector words incl. sentinel
+constexpr int kMainThreads = 256;            // threads per main-kernel workgroup
+constexpr int kPrepThreads = 256;            // threads per pre-pass workgroup
+constexpr int kPrepItems = 4;                // samples per pre-pass thread per chunk
+constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1
+constexpr double kGapDays = 0.5;             // segment break threshold (days)
+
+// One curve of a packed batch, in the (cost-sorted) order tiles are issued.
+struct CurveDesc {
+    int64_t off;        // first sample in the packed arrays
+    int32_t len;        // samples
+    int32_t W;          // window (odd)
+    int32_t tile;       // output positions per tile
+    int32_t tile_base;  // index of this curve's first tile in the tile list
+};
+static_assert(sizeof(CurveDesc) == 24, "CurveDesc layout");
+
+// Segment record written by the pre-pass at segtab[curve.off + segment id]:
+//   x = first valid index, y = last valid index (curve-local),
+//   z = valid samples before the segment, w = valid samples through its end.
+// A segment is live when w - z >= max(1, W / 3).
+
+// Tile record written by the pre-pass: x = index into the curve table,
+// y = first output position (curve-local).
+
+}  // namespace umi

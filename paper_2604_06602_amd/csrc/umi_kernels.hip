@@ -1,0 +1,542 @@
+// HIP kernels of the UMI library for CDNA4 (gfx950).
+//
+// Two kernels run per batch, both on the caller's stream:
+//
+//   umi_prepass_kernel  one workgroup per curve.  Validity and segmentation
+//                       (gap handling, minimum segment length W/3 of
+//                       Section 4.4): a chunked block scan writes a segment id
+//                       per sample and one record per segment, and lays out the
+//                       curve's tile list for the main kernel.
+//
+//   umi_main_kernel     tiles of consecutive output positions.  A workgroup
+//                       stages a tile plus its W-1 halo from HBM once, keeps the
+//                       valid samples compacted in LDS, sorts (key, index) pairs
+//                       of the staged samples once (bitonic network in LDS), and
+//                       builds a wavelet matrix over the sorted ranks.  Every
+//                       lane then takes one window at a time:
+//                         Phase 1 (Section 2.1): exact median as the k-th
+//                           smallest rank in the window's index range, one
+//                           O(log N) wavelet descent -- the sort is shared by
+//                           all windows of the tile;
+//                         Phase 2 (Section 2.2, Eq. 1): upper-RMS scale;
+//                         Phase 3 (Section 2.3, Eqs. 2-4): asymmetric bisquare
+//                           iterations in the residual form
+//                           mu <- mu + sum(w u) / (k sum(w)), k = 1/(c s),
+//                           which is Eq. 4 rewritten around the current mu.
+//                       Launched either persistently (a grid sized to the chip
+//                       pops tiles from a device counter) or one workgroup per
+//                       tile.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "umi_internal.h"
+
+namespace umi {
+
+// ---------------------------------------------------------------------------
+// small wave / block helpers (64-lane wavefronts)
+
+__device__ __forceinline__ int wave_incl_sum(int x)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Inclusive "latest valid sample" scan: the largest index seen so far (-1 if
+// none) together with its time.
+__device__ __forceinline__ void wave_incl_latest(int& idx, double& t)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int yi = __shfl_up(idx, d, 64);
+        double yt = __shfl_up(t, d, 64);
+        if (lane >= d && yi > idx) {
+            idx = yi;
+            t = yt;
+        }
+    }
+}
+
+// Exclusive block-wide sum over kPrepThreads threads; `total` gets the sum.
+__device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
+{
+    const int incl = wave_incl_sum(x);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) sh[w] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kPrepThreads / 64; ++i) {
+        int v = sh[i];
+        before += (i < w) ? v : 0;
+        tot += v;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - x;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-pass: segments and tiles.
+
+__global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
+    const float* __restrict__ flux, const double* __restrict__ time,
+    const CurveDesc* __restrict__ curves, int curve_first,
+    int32_t* __restrict__ segid, int4* __restrict__ segtab,
+    int2* __restrict__ tiles, uint32_t* __restrict__ counter)
+{
+    __shared__ int sh_li[kPrepThreads / 64];
+    __shared__ double sh_lt[kPrepThreads / 64];
+    __shared__ int sh_a[kPrepThreads / 64];
+    __shared__ int sh_b[kPrepThreads / 64];
+
+    const int cidx = curve_first + (int)blockIdx.x;
+    const CurveDesc cd = curves[cidx];
+    if (counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+
+    const int ntiles = cd.len > 0 ? (cd.len + cd.tile - 1) / cd.tile : 0;
+    for (int t = threadIdx.x; t < ntiles; t += kPrepThreads)
+        tiles[cd.tile_base + t] = make_int2(cidx, t * cd.tile);
+
+    const float* f = flux + cd.off;
+    const double* tm = time ? time + cd.off : nullptr;
+    int32_t* sid = segid + cd.off;
+    int* tab = reinterpret_cast<int*>(segtab + cd.off);
+
+    // carries from earlier chunks (uniform over the block)
+    int c_idx = -1;    // latest valid index
+    double c_t = 0.0;  // its time
+    int c_vc = 0;      // valid samples so far
+    int c_ns = 0;      // segments so far
+
+    const int w = threadIdx.x >> 6;
+    const int lane = __lane_id();
+
+    for (int base = 0; base < cd.len; base += kPrepThreads * kPrepItems) {
+        const int e0 = base + (int)threadIdx.x * kPrepItems;
+        bool v[kPrepItems];
+        double t[kPrepItems];
+        int a_idx = -1, a_cnt = 0;
+        double a_t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPrepItems; ++q) {
+            const int e = e0 + q;
+            bool ok = false;
+            double tv = 0.0;
+            if (e < cd.len) {
+                ok = isfinite(f[e]);
+                if (tm) {
+                    tv = tm[e];
+                    ok = ok && isfinite(tv);
+                }
+            }
+            v[q] = ok;
+            t[q] = tv;
+            if (ok) {
+                a_idx = e;
+                a_t = tv;
+                ++a_cnt;
+            }
+        }
+
+        // latest valid sample before this thread's items, and valid count
+        int li = a_idx;
+        double lt = a_t;
+        wave_incl_latest(li, lt);
+        int ex_i = __shfl_up(li, 1, 64);
+        double ex_t = __shfl_up(lt, 1, 64);
+        if (lane == 0) {
+            ex_i = -1;
+            ex_t = 0.0;
+        }
+        if (lane == 63) {
+            sh_li[w] = li;
+            sh_lt[w] = lt;
+        }
+        int tot_cnt;
+        const int ex_cnt = block_excl_sum(a_cnt, sh_a, tot_cnt);  // syncs
+        int blk_i = -1;
+        double blk_t = 0.0;
+        for (int i = 0; i < kPrepThreads / 64; ++i) {
+            const int wi = sh_li[i];
+            if (wi > blk_i) {
+                blk_i = wi;
+                blk_t = sh_lt[i];
+            }
+            if (i + 1 == w && ex_i < 0) {
+                // nothing earlier in this wave: take the lower waves' latest
+                ex_i = blk_i;
+                ex_t = blk_t;
+            }
+        }
+        if (ex_i < 0) {
+            ex_i = c_idx;
+            ex_t = c_t;
+        }
+
+        // segment starts among this thread's items
+        bool st[kPrepItems];
+        int prev_hi[kPrepItems];
+        int vc_at[kPrepItems];
+        int n_st = 0;
+        int pi = ex_i;
+        double pt = ex_t;
+        int vc = c_vc + ex_cnt;
+#pragma unroll
+        for (int q = 0; q < kPrepItems; ++q) {
+            st[q] = false;
+            prev_hi[q] = -1;
+            vc_at[q] = vc;
+            if (v[q]) {
+                st[q] = (pi < 0) || (tm != nullptr && (t[q] - pt) > kGapDays);
+                prev_hi[q] = pi;
+                n_st += st[q] ? 1 : 0;
+                pi = e0 + q;
+                pt = t[q];
+                ++vc;
+            }
+        }
+        int tot_st;
+        const int ex_st = block_excl_sum(n_st, sh_b, tot_st);  // syncs
+        int s = c_ns + ex_st - 1;
+#pragma unroll
+        for (int q = 0; q < kPrepItems; ++q) {
+            const int e = e0 + q;
+            if (e >= cd.len) break;
+            if (v[q]) {
+                if (st[q]) {
+                    ++s;
+                    tab[4 * s + 0] = e;
+                    tab[4 * s + 2] = vc_at[q];
+                    if (s > 0) {
+                        tab[4 * (s - 1) + 1] = prev_hi[q];
+                        tab[4 * (s - 1) + 3] = vc_at[q];
+                    }
+                }
+                sid[e] = s;
+            } else {
+                sid[e] = -1;
+            }
+        }
+        if (blk_i >= 0) {
+            c_idx = blk_i;
+            c_t = blk_t;
+        }
+        c_vc += tot_cnt;
+        c_ns += tot_st;
+        __syncthreads();  // sh_li / sh_lt reused by the next chunk
+    }
+    if (threadIdx.x == 0 && c_ns > 0) {
+        tab[4 * (c_ns - 1) + 1] = c_idx;
+        tab[4 * (c_ns - 1) + 3] = c_vc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Main kernel.
+
+// IEEE-754 totalOrder of float32 as an unsigned key, and back.
+__device__ __forceinline__ uint32_t order_key(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_value(uint32_t k)
+{
+    const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(b);
+}
+
+struct MainSmem {
+    uint64_t sortbuf[kStageMax];          // (key << 32 | compacted index)
+    float xv[kStageMax];                  // compacted valid samples
+    uint16_t seq[2][kStageMax];           // wavelet-matrix level sequences
+    uint64_t bits[kStageLog2][kWords];    // wavelet-matrix level bit vectors
+    uint32_t pre[kStageLog2][kWords];     // ones before each word
+    uint32_t zeros[kStageLog2];           // zeros per level
+    uint64_t vbits[kWords];               // staged-sample validity
+    uint32_t vpre[kWords];
+    int tile;
+    int nvalid;
+};
+
+__device__ __forceinline__ uint32_t rank1(const uint64_t* bits, const uint32_t* pre, uint32_t i)
+{
+    const uint32_t w = i >> 6;
+    const uint64_t m = (1ull << (i & 63u)) - 1ull;
+    return pre[w] + (uint32_t)__popcll(bits[w] & m);
+}
+
+// Ones-before prefix over `nw` words, computed by wave 0; returns total ones
+// in lane 0's view through `total_out` (written to LDS by the caller).
+__device__ __forceinline__ void word_prefix(const uint64_t* bits, uint32_t* pre, int nw, uint32_t* total_out)
+{
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int c = lane < nw ? __popcll(bits[lane]) : 0;
+        const int incl = wave_incl_sum(c);
+        if (lane < nw) pre[lane] = (uint32_t)(incl - c);
+        if (lane == 63) *total_out = (uint32_t)incl;
+    }
+}
+
+// k-th smallest (0-based) value of the level-0 sequence within [s, e).
+__device__ __forceinline__ uint32_t wavelet_kth(const MainSmem& sm, int levels, uint32_t s, uint32_t e, uint32_t k)
+{
+    uint32_t r = 0;
+    for (int l = 0; l < levels; ++l) {
+        const uint32_t os = rank1(sm.bits[l], sm.pre[l], s);
+        const uint32_t oe = rank1(sm.bits[l], sm.pre[l], e);
+        const uint32_t zs = s - os, ze = e - oe;
+        const uint32_t nz = ze - zs;
+        if (k < nz) {
+            s = zs;
+            e = ze;
+        } else {
+            k -= nz;
+            s = sm.zeros[l] + os;
+            e = sm.zeros[l] + oe;
+            r |= 1u << (levels - 1 - l);
+        }
+    }
+    return r;
+}
+
+// Phase 3 sweep over one window: returns sum(w) and sum(w*u) for the
+// current location, where u = x*k + b = (x - mu)/(c s).  kMin selects the
+// asymmetric branch as min(u, alpha*u) (alpha >= 1) or max (alpha < 1): both
+// equal alpha*u for u < 0 and u for u >= 0 (Eq. 2).
+template <bool kMin>
+__device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int ca, int cb,
+                                              float k, float b, float alpha, float& sw_out,
+                                              float& swu_out)
+{
+    float sw = 0.0f, swu = 0.0f;
+#pragma unroll 4
+    for (int j = ca; j < cb; ++j) {
+        const float u = __builtin_fmaf(xv[j], k, b);
+        const float au = alpha * u;
+        const float ue = kMin ? __builtin_fminf(u, au) : __builtin_fmaxf(u, au);
+        // Eq. 3: (1 - ue^2)^2 on |ue| < 1, else 0.  1 - ue^2 <= 1 always, so
+        // clamping to [0, 1] is exactly max(., 0).
+        const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
+        const float wgt = t * t;
+        sw += wgt;
+        swu = __builtin_fmaf(wgt, u, swu);
+    }
+    sw_out = sw;
+    swu_out = swu;
+}
+
+template <bool kMin>
+__device__ __forceinline__ float bisquare(const float* __restrict__ xv, int ca, int cb, float m,
+                                          float k, float alpha, int iters)
+{
+    float mu = m;
+    for (int it = 0; it < iters; ++it) {
+        float sw, swu;
+        bisquare_sums<kMin>(xv, ca, cb, k, -mu * k, alpha, sw, swu);
+        if (!(sw > 0.0f)) break;  // no weight left: keep mu
+        mu = mu + swu / (sw * k);  // Eq. 4 in residual form
+    }
+    return mu;
+}
+
+__global__ __launch_bounds__(kMainThreads) void umi_main_kernel(
+    const float* __restrict__ flux, const int32_t* __restrict__ segid,
+    const int4* __restrict__ segtab, const CurveDesc* __restrict__ curves,
+    const int2* __restrict__ tiles, int tile_first, int tile_end,
+    uint32_t* __restrict__ counter, float alpha, float c, int iters,
+    float* __restrict__ trend, float* __restrict__ median)
+{
+    __shared__ MainSmem sm;
+    const int tid = threadIdx.x;
+    const int lane = __lane_id();
+    const int wave = tid >> 6;
+    const float nanf_ = __builtin_nanf("");
+
+    for (int round = 0;; ++round) {
+        if (tid == 0)
+            sm.tile = counter ? tile_first + (int)atomicAdd(counter, 1u)
+                              : tile_first + (int)blockIdx.x + round * (int)gridDim.x;
+        __syncthreads();
+        const int tile = sm.tile;
+        if (tile >= tile_end) break;
+
+        const int2 td = tiles[tile];
+        const CurveDesc cd = curves[td.x];
+        const int h = (cd.W - 1) >> 1;
+        const int t0 = td.y;
+        const int t1 = min(t0 + cd.tile, cd.len);
+        const int s0 = max(t0 - h, 0);
+        const int s1 = min(t1 + h, cd.len);
+        const int N = s1 - s0;  // <= kStageMax, guaranteed by the host
+        const float* f = flux + cd.off + s0;
+        const int32_t* sg = segid + cd.off + s0;
+
+        // --- staged validity bit vector (valid = finite flux and time) ---
+        const int nwv = (N >> 6) + 1;
+        for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
+            const int i = i0 + lane;
+            const bool ok = (i < N) && (sg[i] >= 0);
+            const uint64_t bal = __ballot(ok);
+            if (lane == 0) sm.vbits[i0 >> 6] = bal;
+        }
+        __syncthreads();
+        word_prefix(sm.vbits, sm.vpre, nwv, reinterpret_cast<uint32_t*>(&sm.nvalid));
+        __syncthreads();
+        const int nv = sm.nvalid;
+        int npad = 64;
+        while (npad < nv) npad <<= 1;
+        int levels = 6;
+        while ((1 << levels) < npad) ++levels;
+
+        // --- compaction: values in index order, (key, index) for the sort ---
+        for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
+            const int i = i0 + lane;
+            if (i < N && sg[i] >= 0) {
+                const float x = f[i];
+                const uint32_t ci = rank1(sm.vbits, sm.vpre, (uint32_t)i);
+                sm.xv[ci] = x;
+                sm.sortbuf[ci] = ((uint64_t)order_key(x) << 32) | ci;
+            }
+        }
+        for (int i = nv + tid; i < npad; i += kMainThreads) sm.sortbuf[i] = ~0ull;
+        __syncthreads();
+
+        // --- bitonic sort of sortbuf[0, npad) ascending ---
+        for (int kk = 2; kk <= npad; kk <<= 1) {
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int cix = tid; cix < (npad >> 1); cix += kMainThreads) {
+                    const int i = 2 * cix - (cix & (jj - 1));
+                    const int l = i + jj;
+                    const uint64_t a = sm.sortbuf[i], b = sm.sortbuf[l];
+                    const bool asc = (i & kk) == 0;
+                    if ((a > b) == asc) {
+                        sm.sortbuf[i] = b;
+                        sm.sortbuf[l] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // --- wavelet matrix over the sequence rank_of[compacted index] ---
+        for (int r = tid; r < npad; r += kMainThreads) {
+            if (r < nv)
+                sm.seq[0][(uint32_t)(sm.sortbuf[r] & 0xffffffffull)] = (uint16_t)r;
+            else
+                sm.seq[0][r] = (uint16_t)(npad - 1);
+        }
+        __syncthreads();
+        const int nwl = (npad >> 6) + 1;
+        for (int l = 0; l < levels; ++l) {
+            const uint16_t* cur = sm.seq[l & 1];
+            uint16_t* nxt = sm.seq[(l + 1) & 1];
+            const int bit = levels - 1 - l;
+            for (int i0 = wave * 64; i0 < nwl * 64; i0 += kMainThreads) {
+                const int i = i0 + lane;
+                const bool one = (i < npad) && (((cur[i < npad ? i : 0] >> bit) & 1) != 0);
+                const uint64_t bal = __ballot(one);
+                if (lane == 0) sm.bits[l][i0 >> 6] = bal;
+            }
+            __syncthreads();
+            uint32_t ones_total;
+            word_prefix(sm.bits[l], sm.pre[l], nwl, &sm.zeros[l]);
+            __syncthreads();
+            if (tid == 0) {
+                ones_total = sm.zeros[l];
+                sm.zeros[l] = (uint32_t)npad - ones_total;
+            }
+            __syncthreads();
+            const uint32_t z = sm.zeros[l];
+            for (int i = tid; i < npad; i += kMainThreads) {
+                const uint16_t val = cur[i];
+                const uint32_t o = rank1(sm.bits[l], sm.pre[l], (uint32_t)i);
+                const bool one = ((val >> bit) & 1) != 0;
+                nxt[one ? z + o : (uint32_t)i - o] = val;
+            }
+            __syncthreads();
+        }
+
+        // --- one window per lane at a time ---
+        const int m_min = max(1, cd.W / 3);
+        for (int p = t0 + tid; p < t1; p += kMainThreads) {
+            const int64_t gp = cd.off + p;
+            float out_t = nanf_, out_m = nanf_;
+            const int sidp = segid[gp];
+            if (sidp >= 0) {
+                const int4 seg = segtab[cd.off + sidp];
+                if (seg.w - seg.z >= m_min) {
+                    const int a = max(p - h, seg.x) - s0;
+                    const int b = min(p + h, seg.y) - s0 + 1;
+                    const uint32_t ca = rank1(sm.vbits, sm.vpre, (uint32_t)a);
+                    const uint32_t cb = rank1(sm.vbits, sm.vpre, (uint32_t)b);
+                    const uint32_t n = cb - ca;  // >= 1: p itself is valid
+                    const uint32_t r = wavelet_kth(sm, levels, ca, cb, (n - 1) >> 1);
+                    const float m = key_value((uint32_t)(sm.sortbuf[r] >> 32));
+                    // Phase 2, Eq. 1: upper-RMS about the median
+                    float ssq = 0.0f;
+                    int nplus = 0;
+                    for (uint32_t j = ca; j < cb; ++j) {
+                        const float d = sm.xv[j] - m;
+                        if (d > 0.0f) {
+                            ssq = __builtin_fmaf(d, d, ssq);
+                            ++nplus;
+                        }
+                    }
+                    float mu = m;
+                    if (nplus > 0 && iters > 0) {
+                        const float s = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
+                        const float k = 1.0f / (c * s);
+                        if (s > 0.0f && isfinite(k)) {
+                            mu = (alpha >= 1.0f)
+                                     ? bisquare<true>(sm.xv, (int)ca, (int)cb, m, k, alpha, iters)
+                                     : bisquare<false>(sm.xv, (int)ca, (int)cb, m, k, alpha, iters);
+                        }
+                    }
+                    out_t = mu;
+                    out_m = m;
+                }
+            }
+            trend[gp] = out_t;
+            if (median) median[gp] = out_m;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch wrappers (the host library calls only these).
+
+hipError_t launch_prepass(const float* flux, const double* time, const CurveDesc* curves,
+                          int curve_first, int n_curves, int32_t* segid, int4* segtab,
+                          int2* tiles, uint32_t* counter, hipStream_t stream)
+{
+    if (n_curves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(umi_prepass_kernel, dim3(n_curves), dim3(kPrepThreads), 0, stream, flux,
+                       time, curves, curve_first, segid, segtab, tiles, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_main(const float* flux, const int32_t* segid, const int4* segtab,
+                       const CurveDesc* curves, const int2* tiles, int tile_first, int tile_end,
+                       uint32_t* counter, int grid, float alpha, float c, int iters, float* trend,
+                       float* median, hipStream_t stream)
+{
+    if (tile_end <= tile_first || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(umi_main_kernel, dim3(grid), dim3(kMainThreads), 0, stream, flux, segid,
+                       segtab, curves, tiles, tile_first, tile_end, counter, alpha, c, iters,
+                       trend, median);
+    return hipGetLastError();
+}
+
+}  // namespace umi

@@ -1,0 +1,121 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "umi.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2604_06602_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(umi_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["umi_detrend", "umi_detrend_batch", "umi_window_from_cadence", "umi_last_error",
+              "umi_release", "umi_set_tuning", "umi_version", "umi_debug_inject_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib.lib, name), name
+
+
+def test_library_is_the_in_tree_hip_build(lib):
+    assert os.path.dirname(lib.LIB_PATH) == os.path.join(ROOT, "paper_2604_06602_amd")
+    assert lib.version().startswith("umi-mi355x")
+
+
+def test_window_rule(lib):
+    assert lib.window_from_cadence(2 / 1440) == 361
+    assert lib.window_from_cadence(29.4 / 1440) == 25
+    assert lib.window_from_cadence(30 / 1440) == 25
+    assert lib.window_from_cadence(2 / 1440, 1.5) == 1081
+    assert lib.window_from_cadence(0.0) == -1
+    assert lib.window_from_cadence(float("nan")) == -1
+    assert lib.window_from_cadence(2 / 1440, -1) == -1
+
+
+def test_window_rule_agrees_with_oracle(lib, oracle_lib):
+    for cad in [0.5, 1, 2, 10, 20, 29.4, 30, 60]:
+        for wd in [0.25, 0.5, 1.0, 1.5]:
+            assert lib.window_from_cadence(cad / 1440, wd) == oracle_lib.window_from_cadence(cad / 1440, wd)
+
+
+def _raw_batch(lib, lengths, W, alpha=2.0, c=5.0, iters=5, flux=1, trend=1, launch=None):
+    lengths = np.asarray(lengths, np.int64)
+    Wa = np.asarray(W, np.int32)
+    lp = ctypes.byref(launch) if launch is not None else None
+    return lib.lib.umi_detrend_batch(
+        ctypes.c_void_p(flux) if flux else None, None,
+        lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), lengths.size,
+        Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), alpha, c, iters,
+        ctypes.c_void_p(trend) if trend else None, None, lp, None)
+
+
+@pytest.mark.parametrize("W,alpha,c,iters,status", [
+    (4, 2.0, 5.0, 5, 1), (0, 2.0, 5.0, 5, 1), (-3, 2.0, 5.0, 5, 1),
+    (361, 0.0, 5.0, 5, 1), (361, -1.0, 5.0, 5, 1), (361, float("nan"), 5.0, 5, 1),
+    (361, float("inf"), 5.0, 5, 1), (361, 2.0, 0.0, 5, 1), (361, 2.0, float("nan"), 5, 1),
+    (361, 2.0, 5.0, -1, 1), (2049, 2.0, 5.0, 5, 4),
+])
+def test_invalid_arguments_rejected_before_launch(lib, W, alpha, c, iters, status):
+    st = _raw_batch(lib, [10], [W], alpha, c, iters)
+    assert st == status
+    assert lib.last_error()
+
+
+def test_other_invalid_arguments(lib):
+    assert _raw_batch(lib, [-1], [5]) == 1
+    assert _raw_batch(lib, [10], [5], flux=0) == 1
+    assert _raw_batch(lib, [10], [5], trend=0) == 1
+    bad_mode = lib.Launch(7, 0, 0, 0, None, None)
+    assert _raw_batch(lib, [10], [5], launch=bad_mode) == 1
+    assert _raw_batch(lib, [10], [5], launch=lib.Launch(0, -1, 0, 0, None, None)) == 1
+    assert _raw_batch(lib, [10], [5], launch=lib.Launch(0, 0, 0, 3, None, None)) == 1
+    assert lib.lib.umi_detrend(None, None, -5, 5, 2.0, 5.0, 5, None, None, None) == 1
+    # a batch whose second curve is bad is rejected as a whole
+    assert _raw_batch(lib, [10, 10], [5, 6]) == 1
+
+
+def test_empty_batches_are_noops(lib):
+    assert _raw_batch(lib, [], []) == 0
+    assert _raw_batch(lib, [0, 0], [5, 7], flux=0, trend=0) == 0
+    assert lib.lib.umi_detrend(None, None, 0, 5, 2.0, 5.0, 5, None, None, None) == 0
+
+
+def test_injected_error_propagates_once(lib):
+    lib.debug_inject_error(lib.UMI_ERR_DEVICE)
+    assert _raw_batch(lib, [0], [5]) == lib.UMI_ERR_DEVICE
+    assert "injected" in lib.last_error()
+    assert _raw_batch(lib, [0], [5]) == 0
+    with pytest.raises(lib.UmiError) as ei:
+        lib.debug_inject_error(lib.UMI_ERR_NO_MEMORY)
+        lib._check(_raw_batch(lib, [0], [5]))
+    assert ei.value.status == lib.UMI_ERR_NO_MEMORY
+
+
+def test_tuning_table_parsing(lib):
+    lib.set_tuning("# W_max tile groups\n31 2000 4\n127 1500 3\n\n2047 0 0\n")
+    lib.set_tuning(None)
+    for bad in ["31 2000", "31 2000 4 9", "127 10 2\n31 10 2", "x 1 2", "31 -1 2", "31 10 99"]:
+        with pytest.raises(lib.UmiError):
+            lib.set_tuning(bad)
+    lib.set_tuning(None)
