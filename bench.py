@@ -29,13 +29,36 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_window(W: int, iters: int) -> int:
-    """Algorithmic FP32 work of one window (add/sub/mul = 1, fma = 2; compares,
-    selects and the per-window divides and square root not counted):
-    Phase 2 costs 3 per sample (subtract, fused square-accumulate), each
-    Phase 3 iteration 8 per sample (residual 1, scale 1, 1-u^2 2, square 1,
-    two accumulations 1 + 2)."""
-    return W * (3 + 8 * iters)
+# Algorithmic FP32 work per window sample (add/sub/mul = 1, fma = 2; compares,
+# selects, the median and the per-window divides and square root not counted):
+# Phase 2 costs 3 (subtract, fused square-accumulate); each Phase 3 iteration
+# costs 8 (residual 1, scaling 1, 1 - u^2 2, square 1, two accumulations 1 + 2).
+
+
+def window_sizes(batch, gap_days: float = 0.5) -> np.ndarray:
+    """Samples n in each output's window (0 where the output is NaN), counted
+    on the host from the input layout alone -- valid samples, segments broken
+    at time steps above `gap_days`, segments shorter than W/3 dropped,
+    windows cut at segment ends.  Used only to count algorithmic work."""
+    out = np.zeros(batch.n_samples, np.int64)
+    for b in range(batch.n_curves):
+        f, t, W = batch.curve(b)
+        o = int(batch.offsets[b])
+        h = (W - 1) // 2
+        valid = np.isfinite(f) & np.isfinite(t)
+        idx = np.flatnonzero(valid)
+        if idx.size == 0:
+            continue
+        breaks = np.flatnonzero(np.diff(t[idx]) > gap_days) + 1
+        for seg in np.split(idx, breaks):
+            if seg.size < max(1, W // 3):
+                continue
+            lo, hi = seg[0], seg[-1]
+            csum = np.concatenate([[0], np.cumsum(valid[lo:hi + 1])])
+            a = np.maximum(seg - h, lo) - lo
+            e = np.minimum(seg + h, hi) - lo + 1
+            out[o + seg] = csum[e] - csum[a]
+    return out
 
 
 def cpu_baseline(batch, budget_s: float = 15.0):
@@ -44,7 +67,7 @@ def cpu_baseline(batch, budget_s: float = 15.0):
     import oracle
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    probe = 8
+    probe = max(8, int(cores))  # one curve per thread, so the probe sees the parallel rate
     sub = batch_prefix(batch, probe)
     t0 = time.perf_counter()
     oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
@@ -61,6 +84,32 @@ def cpu_baseline(batch, budget_s: float = 15.0):
                       % (n, windows, cores, dt)}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "umi_main_kernel__tess_batch_1000x18k_w361.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_06602_amd", "csrc", f)
+                  for f in ("umi_kernels.hip", "umi_internal.h")]
+
+
+def counted_traffic():
+    """HBM bytes per main-kernel launch from the committed counter summary,
+    or None when the kernel sources changed after those counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_source_sha256:", "hbm_traffic_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+        return None
+    try:
+        return int(fields["hbm_traffic_bytes_per_launch"].strip())
+    except (KeyError, ValueError):
+        return None
+
+
 def batch_prefix(batch, n):
     import synth
     return synth.lightcurves.pack([batch.curve(i) for i in range(n)])
@@ -70,10 +119,13 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", choices=["persistent", "per-curve"], default="persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (to scale "
+                         "HBM byte counters) and exit")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: the estimate shards over curves with no exchange, "
@@ -82,6 +134,16 @@ def main(argv=None):
         return 2
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}))
+        return 0
 
     import paper_2604_06602_amd as umi
     import synth
@@ -107,22 +169,26 @@ def main(argv=None):
                                umi.LaunchOptions(mode=mode, main_start=ev0, main_stop=ev1),
                                stream)
 
-    log("warmup %d" % args.warmup)
-    for _ in range(max(1, args.warmup)):
-        step()
-    torch.cuda.synchronize()
-    windows = int(torch.isfinite(trend).sum().item())
-
+    # host-side preparation first, so the GPU does not idle between the
+    # warm-up and the timed steps (its clock drops when idle)
+    nwin = window_sizes(batch)
+    window_samples = int(nwin.sum())
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     for a, b in evs:  # create the HIP events before handing them to the library
         a.record(stream)
         b.record(stream)
-    torch.cuda.synchronize()
-
-    log("timing %d steps" % args.steps)
     t_start = torch.cuda.Event(enable_timing=True)
     t_stop = torch.cuda.Event(enable_timing=True)
+    step()
+    torch.cuda.synchronize()
+    windows = int(torch.isfinite(trend).sum().item())
+    if int((nwin > 0).sum()) != windows:
+        raise RuntimeError("host window count %d != finite outputs %d" % ((nwin > 0).sum(), windows))
+
+    log("warmup %d, then timing %d steps" % (args.warmup, args.steps))
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record(stream)
@@ -133,11 +199,14 @@ def main(argv=None):
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_stop)
     ms_step = total_ms / args.steps
-    main_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    main_each = [a.elapsed_time(b) for a, b in evs]
+    main_ms = float(np.mean(main_each))
     value = windows / (ms_step * 1e-3)
-    flop_launch = windows * flops_per_window(W, iters)
+    # algorithmic work: Phase 2 at 3 and each Phase 3 iteration at 8 FLOP per window sample
+    flop_launch = window_samples * (3 + 8 * iters)
     achieved = flop_launch / (main_ms * 1e-3) / 1e12
     log("step %.3f ms (main %.3f ms), wall %.3f s" % (ms_step, main_ms, wall))
+    log("main kernel per step (ms): " + " ".join("%.3f" % v for v in main_each))
 
     out = {
         "metric": METRIC,
@@ -158,9 +227,11 @@ def main(argv=None):
                    "mode": args.mode, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "kernel": "umi_main_kernel",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                      "avg_launch_ms": main_ms, "flop_per_launch": flop_launch,
-                     "flop_per_window": flops_per_window(W, iters)},
+                     "window_samples_per_launch": window_samples,
+                     "flop_per_window_sample": 3 + 8 * iters},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

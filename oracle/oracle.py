@@ -25,14 +25,20 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
 
+def compile_oracle(src: str, out: str) -> str:
+    """gcc, plain -O2, no fast-math."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-Wall",
+           "-Wextra", "-o", tmp, src, "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle into oracle/libumi_oracle.so."""
     if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-Wall",
-               "-Wextra", "-o", tmp, _SRC, "-lm", "-lpthread"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
+        compile_oracle(_SRC, _LIB_PATH)
     return _LIB_PATH
 
 
@@ -41,9 +47,12 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB_PATH):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("UMI_ORACLE_LIB")  # a test may point at a mutated build
+        if not path:
+            if not os.path.exists(_LIB_PATH):
+                build(force=True)
+            path = _LIB_PATH
+        lib = ctypes.CDLL(path)
         lib.umi_oracle_window_from_cadence.restype = ctypes.c_int
         lib.umi_oracle_window_from_cadence.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.umi_oracle_weight.restype = ctypes.c_double

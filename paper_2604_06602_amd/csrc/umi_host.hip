@@ -58,9 +58,18 @@ struct TuneRow {
 std::mutex g_tune_mu;
 std::vector<TuneRow> g_tune;  // empty = built-in defaults
 
-// Built-in default: fill the staged tile (tile + W - 1 = kStageMax) and run
-// as many persistent workgroups per CU as LDS allows.
-int default_tile(int W) { return std::max(1, kStageMax - (W - 1)); }
+// Largest tile whose staged span (tile + W - 1) fits kStageMax.
+int max_tile(int W) { return std::max(1, kStageMax - (W - 1)); }
+
+// Built-in default: the largest tile, cut back to a whole number of
+// workgroup-wide passes when its last pass would leave most lanes idle.
+int default_tile(int W)
+{
+    const int fill = max_tile(W);
+    const int rem = fill % kMainThreads;
+    if (fill >= kMainThreads && rem < kMainThreads / 2) return fill - rem;
+    return fill;
+}
 constexpr int kDefaultGroupsPerCU = 4;
 
 void tuned(int W, int* tile, int* gpc)
@@ -70,7 +79,7 @@ void tuned(int W, int* tile, int* gpc)
     *gpc = kDefaultGroupsPerCU;
     for (const TuneRow& r : g_tune) {
         if (W <= r.w_max) {
-            if (r.tile > 0) *tile = std::min(r.tile, default_tile(W));
+            if (r.tile > 0) *tile = std::min(r.tile, max_tile(W));
             if (r.groups_per_cu > 0) *gpc = r.groups_per_cu;
             break;
         }
@@ -265,7 +274,7 @@ umi_status detrend_batch(const float* flux, const double* time, const int64_t* l
     for (int64_t b = 0; b < n_curves; ++b) {
         int t, g;
         tuned(W[b], &t, &g);
-        if (opt.tile > 0) t = std::min(opt.tile, default_tile(W[b]));
+        if (opt.tile > 0) t = std::min(opt.tile, max_tile(W[b]));
         tile_of[(size_t)b] = t;
     }
     std::vector<int32_t> order;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
 
     for (int base = 0; base < cd.len; base += kPrepThreads * kPrepItems) {
         const int e0 = base + (int)threadIdx.x * kPrepItems;
-        bool v[kPrepItems];
+        uint32_t vmask = 0;  // bit q: item q is valid
         double t[kPrepItems];
         int a_idx = -1, a_cnt = 0;
         double a_t = 0.0;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
                     ok = ok && isfinite(tv);
                 }
             }
-            v[q] = ok;
+            vmask |= (ok ? 1u : 0u) << q;
             t[q] = tv;
             if (ok) {
                 a_idx = e;
@@ -182,47 +182,49 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
         }
 
         // segment starts among this thread's items
-        bool st[kPrepItems];
-        int prev_hi[kPrepItems];
-        int vc_at[kPrepItems];
+        uint32_t smask = 0;  // bit q: item q starts a segment
         int n_st = 0;
-        int pi = ex_i;
-        double pt = ex_t;
-        int vc = c_vc + ex_cnt;
+        {
+            int pi = ex_i;
+            double pt = ex_t;
 #pragma unroll
-        for (int q = 0; q < kPrepItems; ++q) {
-            st[q] = false;
-            prev_hi[q] = -1;
-            vc_at[q] = vc;
-            if (v[q]) {
-                st[q] = (pi < 0) || (tm != nullptr && (t[q] - pt) > kGapDays);
-                prev_hi[q] = pi;
-                n_st += st[q] ? 1 : 0;
-                pi = e0 + q;
-                pt = t[q];
-                ++vc;
+            for (int q = 0; q < kPrepItems; ++q) {
+                if ((vmask >> q) & 1u) {
+                    const bool st = (pi < 0) || (tm != nullptr && (t[q] - pt) > kGapDays);
+                    smask |= (st ? 1u : 0u) << q;
+                    n_st += st ? 1 : 0;
+                    pi = e0 + q;
+                    pt = t[q];
+                }
             }
         }
         int tot_st;
         const int ex_st = block_excl_sum(n_st, sh_b, tot_st);  // syncs
-        int s = c_ns + ex_st - 1;
+        {
+            int s = c_ns + ex_st - 1;
+            int pi = ex_i;               // previous valid index
+            int vc = c_vc + ex_cnt;      // valid samples before item q
 #pragma unroll
-        for (int q = 0; q < kPrepItems; ++q) {
-            const int e = e0 + q;
-            if (e >= cd.len) break;
-            if (v[q]) {
-                if (st[q]) {
-                    ++s;
-                    tab[4 * s + 0] = e;
-                    tab[4 * s + 2] = vc_at[q];
-                    if (s > 0) {
-                        tab[4 * (s - 1) + 1] = prev_hi[q];
-                        tab[4 * (s - 1) + 3] = vc_at[q];
+            for (int q = 0; q < kPrepItems; ++q) {
+                const int e = e0 + q;
+                if (e < cd.len) {
+                    if ((vmask >> q) & 1u) {
+                        if ((smask >> q) & 1u) {
+                            ++s;
+                            tab[4 * s + 0] = e;
+                            tab[4 * s + 2] = vc;
+                            if (s > 0) {
+                                tab[4 * (s - 1) + 1] = pi;
+                                tab[4 * (s - 1) + 3] = vc;
+                            }
+                        }
+                        sid[e] = s;
+                        pi = e;
+                        ++vc;
+                    } else {
+                        sid[e] = -1;
                     }
                 }
-                sid[e] = s;
-            } else {
-                sid[e] = -1;
             }
         }
         if (blk_i >= 0) {
@@ -310,19 +312,49 @@ __device__ __forceinline__ uint32_t wavelet_kth(const MainSmem& sm, int levels, 
     return r;
 }
 
+// Number of level-0 values smaller than v within [s, e).
+__device__ __forceinline__ uint32_t wavelet_count_less(const MainSmem& sm, int levels, uint32_t s,
+                                                       uint32_t e, uint32_t v)
+{
+    if (v >> levels) return e - s;  // v beyond every stored value
+    uint32_t cnt = 0;
+    for (int l = 0; l < levels; ++l) {
+        const uint32_t os = rank1(sm.bits[l], sm.pre[l], s);
+        const uint32_t oe = rank1(sm.bits[l], sm.pre[l], e);
+        if ((v >> (levels - 1 - l)) & 1u) {
+            cnt += (e - oe) - (s - os);
+            s = sm.zeros[l] + os;
+            e = sm.zeros[l] + oe;
+        } else {
+            s -= os;
+            e -= oe;
+        }
+    }
+    return cnt;
+}
+
 // Phase 3 sweep over one window: returns sum(w) and sum(w*u) for the
 // current location, where u = x*k + b = (x - mu)/(c s).  kMin selects the
 // asymmetric branch as min(u, alpha*u) (alpha >= 1) or max (alpha < 1): both
 // equal alpha*u for u < 0 and u for u >= 0 (Eq. 2).
+// Phase 3 sweep over the n samples xv[c0], ..., xv[c0 + n - 1] of one
+// window: returns sum(w) and sum(w*u) for the current location, with
+// u = x*k + b = (x - mu)/(c s).  kMin selects the asymmetric branch as
+// min(u, alpha*u) (alpha >= 1) or max (alpha < 1): both equal alpha*u for
+// u < 0 and u for u >= 0 (Eq. 2).  The samples are summed in index order
+// whatever the launch shape, so results do not depend on the tiling.
+// `n` may be a per-lane count or a wave-uniform one; with a uniform count
+// the loop runs on the scalar unit and only the LDS address stays per lane.
 template <bool kMin>
-__device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int ca, int cb,
+__device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int c0, int n,
                                               float k, float b, float alpha, float& sw_out,
                                               float& swu_out)
 {
     float sw = 0.0f, swu = 0.0f;
-#pragma unroll 4
-    for (int j = ca; j < cb; ++j) {
-        const float u = __builtin_fmaf(xv[j], k, b);
+    const float* x = xv + c0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) {
+        const float u = __builtin_fmaf(x[j], k, b);
         const float au = alpha * u;
         const float ue = kMin ? __builtin_fminf(u, au) : __builtin_fmaxf(u, au);
         // Eq. 3: (1 - ue^2)^2 on |ue| < 1, else 0.  1 - ue^2 <= 1 always, so
@@ -337,20 +369,33 @@ __device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int 
 }
 
 template <bool kMin>
-__device__ __forceinline__ float bisquare(const float* __restrict__ xv, int ca, int cb, float m,
+__device__ __forceinline__ float bisquare(const float* __restrict__ xv, int c0, int n, float m,
                                           float k, float alpha, int iters)
 {
     float mu = m;
     for (int it = 0; it < iters; ++it) {
         float sw, swu;
-        bisquare_sums<kMin>(xv, ca, cb, k, -mu * k, alpha, sw, swu);
+        bisquare_sums<kMin>(xv, c0, n, k, -mu * k, alpha, sw, swu);
         if (!(sw > 0.0f)) break;  // no weight left: keep mu
         mu = mu + swu / (sw * k);  // Eq. 4 in residual form
     }
     return mu;
 }
 
-__global__ __launch_bounds__(kMainThreads) void umi_main_kernel(
+// Phase 2 sum of squares above the median over xv[c0 .. c0 + n).
+__device__ __forceinline__ float upper_ssq(const float* __restrict__ xv, int c0, int n, float m)
+{
+    float ssq = 0.0f;
+    const float* x = xv + c0;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) {
+        const float d = __builtin_fmaxf(x[j] - m, 0.0f);
+        ssq = __builtin_fmaf(d, d, ssq);
+    }
+    return ssq;
+}
+
+__global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const float* __restrict__ flux, const int32_t* __restrict__ segid,
     const int4* __restrict__ segtab, const CurveDesc* __restrict__ curves,
     const int2* __restrict__ tiles, int tile_first, int tile_end,
@@ -469,46 +514,70 @@ __global__ __launch_bounds__(kMainThreads) void umi_main_kernel(
 
         // --- one window per lane at a time ---
         const int m_min = max(1, cd.W / 3);
-        for (int p = t0 + tid; p < t1; p += kMainThreads) {
+        for (int base = t0; base < t1; base += kMainThreads) {
+            const int p = base + tid;
             const int64_t gp = cd.off + p;
-            float out_t = nanf_, out_m = nanf_;
-            const int sidp = segid[gp];
-            if (sidp >= 0) {
-                const int4 seg = segtab[cd.off + sidp];
-                if (seg.w - seg.z >= m_min) {
-                    const int a = max(p - h, seg.x) - s0;
-                    const int b = min(p + h, seg.y) - s0 + 1;
-                    const uint32_t ca = rank1(sm.vbits, sm.vpre, (uint32_t)a);
-                    const uint32_t cb = rank1(sm.vbits, sm.vpre, (uint32_t)b);
-                    const uint32_t n = cb - ca;  // >= 1: p itself is valid
-                    const uint32_t r = wavelet_kth(sm, levels, ca, cb, (n - 1) >> 1);
-                    const float m = key_value((uint32_t)(sm.sortbuf[r] >> 32));
-                    // Phase 2, Eq. 1: upper-RMS about the median
-                    float ssq = 0.0f;
-                    int nplus = 0;
-                    for (uint32_t j = ca; j < cb; ++j) {
-                        const float d = sm.xv[j] - m;
-                        if (d > 0.0f) {
-                            ssq = __builtin_fmaf(d, d, ssq);
-                            ++nplus;
-                        }
+            bool live = false;
+            uint32_t ca = 0, n = 0;
+            if (p < t1) {
+                const int sidp = segid[gp];
+                if (sidp >= 0) {
+                    const int4 seg = segtab[cd.off + sidp];
+                    if (seg.w - seg.z >= m_min) {
+                        const int a = max(p - h, seg.x) - s0;
+                        const int b = min(p + h, seg.y) - s0 + 1;
+                        ca = rank1(sm.vbits, sm.vpre, (uint32_t)a);
+                        n = rank1(sm.vbits, sm.vpre, (uint32_t)b) - ca;  // >= 1: p is valid
+                        live = true;
                     }
-                    float mu = m;
-                    if (nplus > 0 && iters > 0) {
-                        const float s = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
-                        const float k = 1.0f / (c * s);
-                        if (s > 0.0f && isfinite(k)) {
-                            mu = (alpha >= 1.0f)
-                                     ? bisquare<true>(sm.xv, (int)ca, (int)cb, m, k, alpha, iters)
-                                     : bisquare<false>(sm.xv, (int)ca, (int)cb, m, k, alpha, iters);
-                        }
-                    }
-                    out_t = mu;
-                    out_m = m;
                 }
             }
-            trend[gp] = out_t;
-            if (median) median[gp] = out_m;
+            // Windows of equal length across the whole wave (the common case)
+            // run their sample loops with a wave-uniform trip count.
+            const uint32_t n_u = __builtin_amdgcn_readfirstlane(n);
+            const bool uniform = __all(live && n == n_u);
+            float out_t = nanf_, out_m = nanf_;
+            if (live) {
+                const uint32_t cb = ca + n;
+                const uint32_t r = wavelet_kth(sm, levels, ca, cb, (n - 1) >> 1);
+                const float m = key_value((uint32_t)(sm.sortbuf[r] >> 32));
+                // Phase 2, Eq. 1: upper-RMS about the median.  The points
+                // strictly above m are the window's elements ranked after the
+                // last tile element numerically equal to m (ties and -0/+0 sit
+                // next to m in the sorted order), counted with one wavelet
+                // descent instead of a compare per sample.
+                uint32_t rh = r;
+                while (rh + 1 < (uint32_t)nv &&
+                       key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m)
+                    ++rh;
+                const uint32_t nplus = n - wavelet_count_less(sm, levels, ca, cb, rh + 1);
+                float ssq;
+                if (uniform)  // wave-uniform branch: separate loop bodies
+                    ssq = upper_ssq(sm.xv, (int)ca, (int)n_u, m);
+                else
+                    ssq = upper_ssq(sm.xv, (int)ca, (int)n, m);
+                float mu = m;
+                if (nplus > 0 && iters > 0) {
+                    const float s = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
+                    const float k = 1.0f / (c * s);
+                    if (s > 0.0f && isfinite(k)) {
+                        if (alpha >= 1.0f) {
+                            if (uniform)
+                                mu = bisquare<true>(sm.xv, (int)ca, (int)n_u, m, k, alpha, iters);
+                            else
+                                mu = bisquare<true>(sm.xv, (int)ca, (int)n, m, k, alpha, iters);
+                        } else {
+                            mu = bisquare<false>(sm.xv, (int)ca, (int)n, m, k, alpha, iters);
+                        }
+                    }
+                }
+                out_t = mu;
+                out_m = m;
+            }
+            if (p < t1) {
+                trend[gp] = out_t;
+                if (median) median[gp] = out_m;
+            }
         }
         __syncthreads();
     }
