@@ -80,8 +80,8 @@ def cpu_baseline(batch, budget_s: float = 15.0):
     windows = int(np.isfinite(tr).sum())
     return {"value": windows / dt, "unit": "window-estimates/s", "cores": int(cores),
             "kind": "oracle",
-            "sample": "first %d of the 1000 curves (%d windows), FP64 C oracle, %d threads, %.1f s"
-                      % (n, windows, cores, dt)}
+            "sample": "first %d of the %d curves (%d windows), FP64 C oracle, %d threads, %.1f s"
+                      % (n, batch.n_curves, windows, cores, dt)}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "umi_main_kernel__tess_batch_1000x18k_w361.md")
@@ -120,7 +120,16 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", type=int, choices=[1, 2, 3], default=1,
+                    help="1: 1000x18k TESS batch, W=361 (headline); 2: 2000 Kepler-like curves "
+                         "of 40k-70k, W=25; 3: 10,000 mixed curves of 1k-120k, W in "
+                         "{25,121,361,721}, 5%% NaN gaps")
     ap.add_argument("--mode", choices=["persistent", "per-curve"], default="persistent")
+    ap.add_argument("--compare-per-curve", action="store_true",
+                    help="also time one launch per curve on the same batch")
+    ap.add_argument("--tuning", default="auto",
+                    help="'auto' (the committed tuning table for this GPU, if any), 'none' "
+                         "(built-in defaults) or a table file")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -151,9 +160,9 @@ def main(argv=None):
     def log(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
-    log("generating workload")
-    batch = synth.config_batch(1)
-    W, alpha, c, iters = 361, 2.0, 5.0, 5
+    log("generating workload %d" % args.workload)
+    batch = synth.config_batch(args.workload)
+    alpha, c, iters = 2.0, 5.0, 5
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     flux = torch.from_numpy(batch.flux).to(dev)
@@ -163,10 +172,24 @@ def main(argv=None):
     Ws = batch.W
     mode = umi.MODE_PERSISTENT if args.mode == "persistent" else umi.MODE_PER_CURVE
     stream = torch.cuda.current_stream()
+    tuning = "built-in defaults"
+    if args.tuning == "auto":
+        from paper_2604_06602_amd import autotune
+        if autotune.apply():
+            tuning = "tuning table " + autotune.cache_key()
+    elif args.tuning.endswith(".json"):
+        from paper_2604_06602_amd import autotune
+        if not autotune.apply(args.tuning):
+            raise SystemExit("no tuning entry for %s in %s" % (autotune.cache_key(), args.tuning))
+        tuning = "tuning table %s from %s" % (autotune.cache_key(), args.tuning)
+    elif args.tuning != "none":
+        umi.set_tuning(open(args.tuning).read())
+        tuning = "tuning table " + args.tuning
 
-    def step(ev0=None, ev1=None):
+    def step(ev0=None, ev1=None, m=None):
         umi.detrend_batch_into(flux, tim, lengths, Ws, trend, None, alpha, c, iters,
-                               umi.LaunchOptions(mode=mode, main_start=ev0, main_stop=ev1),
+                               umi.LaunchOptions(mode=mode if m is None else m,
+                                                 main_start=ev0, main_stop=ev1),
                                stream)
 
     # host-side preparation first, so the GPU does not idle between the
@@ -208,8 +231,30 @@ def main(argv=None):
     log("step %.3f ms (main %.3f ms), wall %.3f s" % (ms_step, main_ms, wall))
     log("main kernel per step (ms): " + " ".join("%.3f" % v for v in main_each))
 
+    per_curve = None
+    if args.compare_per_curve:
+        other = umi.MODE_PER_CURVE if mode == umi.MODE_PERSISTENT else umi.MODE_PERSISTENT
+        k = max(3, args.steps // 4)
+        for _ in range(2):
+            step(m=other)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            step(m=other)
+        b.record(stream)
+        torch.cuda.synchronize()
+        oms = a.elapsed_time(b) / k
+        name = "per-curve" if other == umi.MODE_PER_CURVE else "persistent"
+        per_curve = {"mode": name, "ms_per_step": oms, "value": windows / (oms * 1e-3),
+                     "steps": k, "speedup_of_%s" % args.mode: oms / ms_step}
+        log("%s: %.3f ms per step" % (name, oms))
+
+    wl = {1: "tess_batch_1000x18k_w361", 2: "kepler_ragged_2000x40k-70k_w25",
+          3: "mixed_ragged_10000x1k-120k_wmix"}[args.workload]
     out = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == 1 else "window-estimates/s (%s)" % wl,
         "value": value,
         "unit": "window-estimates/s",
         "n_gpus": 1,
@@ -221,10 +266,11 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "tess_batch_1000x18k_w361", "curves": int(batch.n_curves),
-                   "samples_per_curve": 18000, "W": W, "alpha": alpha, "c": c, "iters": iters,
-                   "nan_gap": "1 day (720 samples) mid-sector", "windows": windows,
-                   "mode": args.mode, "parallelism": "single-gpu"},
+        "config": {"workload": wl, "curves": int(batch.n_curves),
+                   "samples": int(batch.n_samples),
+                   "W": sorted(set(int(w) for w in batch.W)), "alpha": alpha, "c": c,
+                   "iters": iters, "windows": windows, "mode": args.mode, "tuning": tuning,
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "kernel": "umi_main_kernel",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(),
@@ -233,6 +279,10 @@ def main(argv=None):
                      "window_samples_per_launch": window_samples,
                      "flop_per_window_sample": 3 + 8 * iters},
     }
+    if per_curve is not None:
+        out["comparison"] = per_curve
+    if args.workload != 1:
+        out["roofline"]["traffic"] = None  # the committed counters cover workload 1 only
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)

@@ -120,6 +120,51 @@ umi_status umi_detrend_batch(const float* flux, const double* time,
                              int32_t iters, float* trend, float* median,
                              const umi_launch* launch, void* stream);
 
+/*
+ * umi_detrend_gather -- like umi_detrend_batch, but curve b sits at samples
+ * [offsets[b], offsets[b] + lengths[b]) of every per-sample array instead of
+ * back-to-back, so curves resident anywhere in a device arena are batched
+ * without copies.
+ *   offsets  [host] n_curves sample offsets (>= 0); the ranges must not
+ *            overlap (UMI_ERR_INVALID_ARG otherwise).
+ * Samples outside every range are neither read nor written.
+ */
+umi_status umi_detrend_gather(const float* flux, const double* time,
+                              const int64_t* offsets, const int64_t* lengths,
+                              int64_t n_curves, const int32_t* W, float alpha,
+                              float c, int32_t iters, float* trend,
+                              float* median, const umi_launch* launch,
+                              void* stream);
+
+/*
+ * Plans: a replayable launch over fixed device arrays, for serving loops.
+ * umi_plan_create binds the arrays (each `capacity` samples; time and median
+ * may be NULL) and a non-default stream, and allocates the plan's workspace
+ * once.  umi_plan_run stages one batch -- curves at explicit offsets inside
+ * the arrays, as for umi_detrend_gather, at most `max_curves` curves with
+ * W <= max_W -- into one of two pinned staging slots and replays that slot's
+ * hipGraph (copy of the staged tile table, segmentation pre-pass, persistent
+ * estimate kernel; captured on the slot's first use) on the plan's stream.
+ * It allocates no device or pinned memory and returns without synchronising,
+ * except that it waits for the replay that used the same slot two calls earlier.  Results
+ * of a run are in `trend` / `median` once the stream reaches that point.
+ * Calls on one plan are serialised; a plan is used from one device.
+ * umi_plan_destroy waits for the stream and frees everything.
+ * The same errors as umi_detrend_gather apply; a batch that exceeds the plan
+ * (curves, capacity, max_W, tiles) gives UMI_ERR_INVALID_ARG or
+ * UMI_ERR_UNSUPPORTED and launches nothing.
+ */
+typedef struct umi_plan umi_plan;
+
+umi_status umi_plan_create(umi_plan** out, int64_t capacity,
+                           int64_t max_curves, int32_t max_W,
+                           const float* flux, const double* time,
+                           float* trend, float* median, void* stream);
+umi_status umi_plan_run(umi_plan* plan, const int64_t* offsets,
+                        const int64_t* lengths, const int32_t* W,
+                        int64_t n_curves, float alpha, float c, int32_t iters);
+umi_status umi_plan_destroy(umi_plan* plan);
+
 /* Window-size rule of Section 2: round(window_days / cadence_days) | 1.
  * Returns -1 when either argument is not positive and finite. */
 int32_t umi_window_from_cadence(double cadence_days, double window_days);

@@ -11,11 +11,13 @@ from ._lib import (  # noqa: F401
     MODE_PER_CURVE,
     MODE_PERSISTENT,
     LaunchOptions,
+    Plan,
     UmiError,
     debug_inject_error,
     detrend,
     detrend_batch,
     detrend_batch_into,
+    detrend_gather_into,
     last_error,
     release,
     set_tuning,

@@ -46,6 +46,11 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 
 
 def _load():
+    # torch first: libumi.so needs libamdhip64.so.7, and loading it after torch
+    # binds it to torch's HIP runtime (same soname), so the device pointers and
+    # streams torch hands over belong to the runtime the library launches on.
+    # Loaded the other way round a process would hold two HIP runtimes.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libumi.so is not built (%s); run `python -m paper_2604_06602_amd.build` "
                           "or __graft_entry__.build()" % LIB_PATH)
@@ -57,6 +62,18 @@ def _load():
     lib.umi_detrend_batch.argtypes = [_vp, _vp, _i64p, ctypes.c_int64, _i32p, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_int32, _vp, _vp,
                                       ctypes.POINTER(Launch), _vp]
+    lib.umi_detrend_gather.restype = ctypes.c_int
+    lib.umi_detrend_gather.argtypes = [_vp, _vp, _i64p, _i64p, ctypes.c_int64, _i32p,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp, _vp,
+                                       ctypes.POINTER(Launch), _vp]
+    lib.umi_plan_create.restype = ctypes.c_int
+    lib.umi_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
+    lib.umi_plan_run.restype = ctypes.c_int
+    lib.umi_plan_run.argtypes = [_vp, _i64p, _i64p, _i32p, ctypes.c_int64, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_int32]
+    lib.umi_plan_destroy.restype = ctypes.c_int
+    lib.umi_plan_destroy.argtypes = [_vp]
     lib.umi_window_from_cadence.restype = ctypes.c_int32
     lib.umi_window_from_cadence.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.umi_set_tuning.restype = ctypes.c_int
@@ -193,3 +210,89 @@ def detrend(flux, time=None, W=361, alpha=2.0, c=5.0, iters=5, with_median=False
                          _dev_ptr(median, torch.float32, "median", n), _stream_handle(stream))
     _check(st)
     return trend, median
+
+
+def _host_arrays(offsets, lengths, W):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    lengths = np.ascontiguousarray(lengths, dtype=np.int64)
+    Wa = np.ascontiguousarray(np.broadcast_to(np.asarray(W, dtype=np.int32), lengths.shape))
+    if offsets.shape != lengths.shape:
+        raise ValueError("offsets and lengths differ in size")
+    return offsets, lengths, Wa
+
+
+def _span_ptr(t, dtype, name, span):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if t.numel() < span:
+        raise ValueError("%s holds %d samples, curves reach %d" % (name, t.numel(), span))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def detrend_gather_into(flux, time, offsets, lengths, W, trend, median=None, alpha=2.0, c=5.0,
+                        iters=5, launch: LaunchOptions | None = None, stream=None):
+    """Curves at explicit sample offsets of the device arrays (no packing)."""
+    torch = _torch()
+    offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
+    span = int((offsets + np.maximum(lengths, 0)).max()) if lengths.size else 0
+    lp = ctypes.byref(launch.as_struct()) if launch is not None else None
+    st = lib.umi_detrend_gather(_span_ptr(flux, torch.float32, "flux", span),
+                                _span_ptr(time, torch.float64, "time", span),
+                                offsets.ctypes.data_as(_i64p), lengths.ctypes.data_as(_i64p),
+                                lengths.size, Wa.ctypes.data_as(_i32p), float(alpha), float(c),
+                                int(iters), _span_ptr(trend, torch.float32, "trend", span),
+                                _span_ptr(median, torch.float32, "median", span), lp,
+                                _stream_handle(stream))
+    _check(st)
+
+
+class Plan:
+    """A replayable launch (hipGraph per staging slot) over fixed device arrays."""
+
+    def __init__(self, flux, time, trend, median=None, max_curves=1024, max_W=MAX_WINDOW,
+                 stream=None):
+        torch = _torch()
+        cap = flux.numel()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if int(self.stream.cuda_stream) == 0:
+            raise ValueError("a plan needs a non-default stream")
+        self._keep = (flux, time, trend, median)  # the plan holds their pointers
+        h = ctypes.c_void_p()
+        st = lib.umi_plan_create(ctypes.byref(h), cap, int(max_curves), int(max_W),
+                                 _span_ptr(flux, torch.float32, "flux", cap),
+                                 _span_ptr(time, torch.float64, "time", cap),
+                                 _span_ptr(trend, torch.float32, "trend", cap),
+                                 _span_ptr(median, torch.float32, "median", cap),
+                                 ctypes.c_void_p(int(self.stream.cuda_stream)))
+        _check(st)
+        self._h = h
+        self.capacity = cap
+        self.max_curves = int(max_curves)
+        self.max_W = int(max_W)
+
+    def run(self, offsets, lengths, W, alpha=2.0, c=5.0, iters=5):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
+        st = lib.umi_plan_run(self._h, offsets.ctypes.data_as(_i64p),
+                              lengths.ctypes.data_as(_i64p), Wa.ctypes.data_as(_i32p),
+                              lengths.size, float(alpha), float(c), int(iters))
+        _check(st)
+
+    def destroy(self):
+        if self._h is not None:
+            st = lib.umi_plan_destroy(self._h)
+            self._h = None
+            self._keep = None
+            _check(st)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

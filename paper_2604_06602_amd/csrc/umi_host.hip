@@ -1,6 +1,6 @@
 // Host side of the UMI C ABI (include/umi.h): argument checks, the batch
 // packer (cost-sorted curve table), per-(device, stream) workspaces, the
-// tuning table, and the kernel launches.
+// tuning table, the kernel launches, and replayable plans (hipGraph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,7 +10,6 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <numeric>
 #include <sstream>
 #include <string>
 #include <utility>
@@ -21,13 +20,13 @@
 
 namespace umi {
 
-hipError_t launch_prepass(const float* flux, const double* time, const CurveDesc* curves,
-                          int curve_first, int n_curves, int32_t* segid, int4* segtab,
-                          int2* tiles, uint32_t* counter, hipStream_t stream);
+hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
+                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
+                          int4* segtab, int2* tiles, uint32_t* counter, hipStream_t stream);
 hipError_t launch_main(const float* flux, const int32_t* segid, const int4* segtab,
-                       const CurveDesc* curves, const int2* tiles, int tile_first, int tile_end,
-                       uint32_t* counter, int grid, float alpha, float c, int iters, float* trend,
-                       float* median, hipStream_t stream);
+                       const BatchHeader* hdr, const CurveDesc* curves, const int2* tiles,
+                       int tile_first, int tile_count, uint32_t* counter, int grid,
+                       float* trend, float* median, hipStream_t stream);
 
 namespace {
 
@@ -44,6 +43,14 @@ umi_status fail_hip(hipError_t e, const char* where)
 {
     std::string m = std::string(where) + ": " + hipGetErrorString(e);
     return fail(e == hipErrorOutOfMemory ? UMI_ERR_NO_MEMORY : UMI_ERR_DEVICE, m);
+}
+
+bool take_injected(umi_status* s)
+{
+    if (t_inject == UMI_OK) return false;
+    *s = fail(t_inject, "injected error (umi_debug_inject_error)");
+    t_inject = UMI_OK;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -70,7 +77,7 @@ int default_tile(int W)
     if (fill >= kMainThreads && rem < kMainThreads / 2) return fill - rem;
     return fill;
 }
-constexpr int kDefaultGroupsPerCU = 4;
+constexpr int kDefaultGroupsPerCU = 4;  // LDS (37.6 KB) allows four 512-thread groups per CU
 
 void tuned(int W, int* tile, int* gpc)
 {
@@ -87,7 +94,144 @@ void tuned(int W, int* tile, int* gpc)
 }
 
 // ---------------------------------------------------------------------------
-// workspaces, one per (device, stream)
+// argument checks
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+umi_status check_window(int32_t W)
+{
+    if (W < 1 || (W % 2) == 0)
+        return fail(UMI_ERR_INVALID_ARG, "W must be odd and >= 1 (got " + std::to_string(W) + ")");
+    if (W > UMI_MAX_WINDOW)
+        return fail(UMI_ERR_UNSUPPORTED,
+                    "W=" + std::to_string(W) + " exceeds UMI_MAX_WINDOW=" +
+                        std::to_string(UMI_MAX_WINDOW));
+    return UMI_OK;
+}
+
+umi_status check_params(float alpha, float c, int32_t iters)
+{
+    if (!finite_pos(alpha)) return fail(UMI_ERR_INVALID_ARG, "alpha must be finite and > 0");
+    if (!finite_pos(c)) return fail(UMI_ERR_INVALID_ARG, "c must be finite and > 0");
+    if (iters < 0) return fail(UMI_ERR_INVALID_ARG, "iters must be >= 0");
+    return UMI_OK;
+}
+
+// Checks curves at explicit offsets: lengths >= 0, valid windows, ranges
+// pairwise disjoint.  `span` gets max(off + len), `total` the sample count.
+umi_status check_curves(const int64_t* offsets, const int64_t* lengths, int64_t n,
+                        const int32_t* W, int64_t* span, int64_t* total)
+{
+    *span = 0;
+    *total = 0;
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    ranges.reserve((size_t)n);
+    for (int64_t b = 0; b < n; ++b) {
+        if (lengths[b] < 0) return fail(UMI_ERR_INVALID_ARG, "curve lengths must be >= 0");
+        if (lengths[b] > (int64_t)INT32_MAX)
+            return fail(UMI_ERR_UNSUPPORTED, "a curve longer than 2^31-1 samples");
+        if (offsets[b] < 0 || offsets[b] > INT64_MAX - lengths[b])
+            return fail(UMI_ERR_INVALID_ARG, "curve offsets must be >= 0");
+        umi_status st = check_window(W[b]);
+        if (st != UMI_OK) return st;
+        if (lengths[b] > 0) ranges.emplace_back(offsets[b], offsets[b] + lengths[b]);
+        *span = std::max(*span, offsets[b] + lengths[b]);
+        *total += lengths[b];
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second)
+            return fail(UMI_ERR_INVALID_ARG, "curves overlap in the sample arrays");
+    return UMI_OK;
+}
+
+umi_status check_launch(const umi_launch* launch, umi_launch* opt)
+{
+    *opt = umi_launch{UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
+    if (launch) *opt = *launch;
+    if (opt->reserved != 0) return fail(UMI_ERR_INVALID_ARG, "umi_launch.reserved must be 0");
+    if (opt->mode != UMI_MODE_PERSISTENT && opt->mode != UMI_MODE_PER_CURVE)
+        return fail(UMI_ERR_INVALID_ARG, "unknown launch mode");
+    if (opt->tile < 0 || opt->groups_per_cu < 0)
+        return fail(UMI_ERR_INVALID_ARG, "launch tile and groups_per_cu must be >= 0");
+    return UMI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// packer: the curve table in decreasing per-tile cost
+
+struct Packed {
+    std::vector<CurveDesc> curves;      // non-empty curves, cost order
+    std::vector<int64_t> curve_tiles;   // tiles per table entry
+    int64_t ntiles = 0;
+    int gpc = kDefaultGroupsPerCU;      // persistent groups per CU
+};
+
+umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
+                const umi_launch& opt, Packed* out)
+{
+    std::vector<int> tile_of((size_t)n);
+    std::vector<int32_t> order;
+    order.reserve((size_t)n);
+    for (int64_t b = 0; b < n; ++b) {
+        int t, g;
+        tuned(W[b], &t, &g);
+        if (opt.tile > 0) t = std::min(opt.tile, max_tile(W[b]));
+        tile_of[(size_t)b] = t;
+        if (lengths[b] > 0) order.push_back((int32_t)b);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int64_t ca = (int64_t)W[a] * tile_of[(size_t)a];
+        const int64_t cb = (int64_t)W[b] * tile_of[(size_t)b];
+        if (ca != cb) return ca > cb;
+        return lengths[a] > lengths[b];
+    });
+    out->curves.resize(order.size());
+    out->curve_tiles.resize(order.size());
+    out->ntiles = 0;
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int32_t b = order[i];
+        const int64_t nt = (lengths[b] + tile_of[(size_t)b] - 1) / tile_of[(size_t)b];
+        if (out->ntiles + nt > (int64_t)INT32_MAX)
+            return fail(UMI_ERR_UNSUPPORTED, "too many tiles in one batch");
+        CurveDesc& d = out->curves[i];
+        d.off = offsets[b];
+        d.len = (int32_t)lengths[b];
+        d.W = W[b];
+        d.tile = tile_of[(size_t)b];
+        d.tile_base = (int32_t)out->ntiles;
+        out->curve_tiles[i] = nt;
+        out->ntiles += nt;
+    }
+    out->gpc = kDefaultGroupsPerCU;
+    if (!order.empty()) {
+        int t_unused;
+        tuned(W[order[0]], &t_unused, &out->gpc);  // the costliest curve's row
+    }
+    if (opt.groups_per_cu > 0) out->gpc = opt.groups_per_cu;
+    return UMI_OK;
+}
+
+size_t block_bytes(int64_t ncurves)
+{
+    return sizeof(BatchHeader) + (size_t)ncurves * sizeof(CurveDesc);
+}
+
+void write_block(uint8_t* dst, const Packed& p, float alpha, float c, int32_t iters)
+{
+    BatchHeader h = {};
+    h.n_curves = (int32_t)p.curves.size();
+    h.n_tiles = (int32_t)p.ntiles;
+    h.alpha = alpha;
+    h.c = c;
+    h.iters = iters;
+    std::memcpy(dst, &h, sizeof h);
+    if (!p.curves.empty())
+        std::memcpy(dst + sizeof h, p.curves.data(), p.curves.size() * sizeof(CurveDesc));
+}
+
+// ---------------------------------------------------------------------------
+// device buffers of a launch sequence
 
 template <class T>
 hipError_t grow(T** p, int64_t* cap, int64_t need)
@@ -105,75 +249,125 @@ hipError_t grow(T** p, int64_t* cap, int64_t need)
     return e;
 }
 
-struct Workspace {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::mutex mu;
-    int32_t* segid = nullptr;
+struct DeviceBuffers {
+    int32_t* segid = nullptr;   // per sample slot
     int64_t cap_segid = 0;
-    int4* segtab = nullptr;
+    int4* segtab = nullptr;     // per sample slot (used per segment)
     int64_t cap_segtab = 0;
-    CurveDesc* curves = nullptr;
-    int64_t cap_curves = 0;
     int2* tiles = nullptr;
     int64_t cap_tiles = 0;
     uint32_t* counter = nullptr;
     int64_t cap_counter = 0;
-    CurveDesc* h_curves = nullptr;  // pinned staging for the curve table
-    int64_t cap_h_curves = 0;
-    hipEvent_t staged = nullptr;    // last copy out of h_curves
+
+    hipError_t reserve(int64_t span, int64_t ntiles)
+    {
+        hipError_t e;
+        if ((e = grow(&segid, &cap_segid, span)) != hipSuccess) return e;
+        if ((e = grow(&segtab, &cap_segtab, span)) != hipSuccess) return e;
+        if ((e = grow(&tiles, &cap_tiles, ntiles)) != hipSuccess) return e;
+        return grow(&counter, &cap_counter, 1);
+    }
+    bool fits(int64_t span, int64_t ntiles) const
+    {
+        return span <= cap_segid && span <= cap_segtab && ntiles <= cap_tiles && cap_counter >= 1;
+    }
+    void release()
+    {
+        if (segid) (void)hipFree(segid);
+        if (segtab) (void)hipFree(segtab);
+        if (tiles) (void)hipFree(tiles);
+        if (counter) (void)hipFree(counter);
+        *this = DeviceBuffers();
+    }
+};
+
+// Enqueue the pre-pass and estimate kernels for a staged block (header +
+// curve table, at `dblock` on the device by the time the stream reaches them).
+hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, float* median,
+                           const uint8_t* dblock, const DeviceBuffers& b, int mode,
+                           const Packed* p, int prep_grid, int main_grid, hipEvent_t ev0,
+                           hipEvent_t ev1, hipStream_t stream)
+{
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblock);
+    const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
+    hipError_t e;
+    if (mode == UMI_MODE_PERSISTENT) {
+        if ((e = launch_prepass(flux, time, hdr, curves, 0, prep_grid, b.segid, b.segtab, b.tiles,
+                                b.counter, stream)) != hipSuccess)
+            return e;
+        if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
+        if ((e = launch_main(flux, b.segid, b.segtab, hdr, curves, b.tiles, 0, -1, b.counter,
+                             main_grid, trend, median, stream)) != hipSuccess)
+            return e;
+        if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    // one pre-pass and one estimate launch per curve, one workgroup per tile
+    if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
+    for (size_t i = 0; i < p->curves.size(); ++i) {
+        if ((e = launch_prepass(flux, time, hdr, curves, (int)i, 1, b.segid, b.segtab, b.tiles,
+                                nullptr, stream)) != hipSuccess)
+            return e;
+        const int nt = (int)p->curve_tiles[i];
+        if ((e = launch_main(flux, b.segid, b.segtab, hdr, curves, b.tiles,
+                             p->curves[i].tile_base, nt, nullptr, nt, trend, median, stream)) !=
+            hipSuccess)
+            return e;
+    }
+    if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces of the direct calls, one per (device, stream)
+
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    DeviceBuffers buf;
+    uint8_t* dblock = nullptr;   // header + curve table on the device
+    int64_t cap_dblock = 0;
+    uint8_t* hblock = nullptr;   // pinned staging for it
+    int64_t cap_hblock = 0;
+    hipEvent_t staged = nullptr; // last copy out of hblock
     bool staged_pending = false;
 
     void free_all()
     {
-        if (segid) (void)hipFree(segid);
-        if (segtab) (void)hipFree(segtab);
-        if (curves) (void)hipFree(curves);
-        if (tiles) (void)hipFree(tiles);
-        if (counter) (void)hipFree(counter);
-        if (h_curves) (void)hipHostFree(h_curves);
+        buf.release();
+        if (dblock) (void)hipFree(dblock);
+        if (hblock) (void)hipHostFree(hblock);
         if (staged) (void)hipEventDestroy(staged);
-        segid = nullptr;
-        segtab = nullptr;
-        curves = nullptr;
-        tiles = nullptr;
-        counter = nullptr;
-        h_curves = nullptr;
+        dblock = hblock = nullptr;
+        cap_dblock = cap_hblock = 0;
         staged = nullptr;
-        cap_segid = cap_segtab = cap_curves = cap_tiles = cap_counter = cap_h_curves = 0;
         staged_pending = false;
     }
 
     // Make room; if anything must be reallocated, first wait for work already
     // queued on this stream, which may still read the old buffers.
-    hipError_t reserve(int64_t samples, int64_t ncurves, int64_t ntiles)
+    hipError_t reserve(int64_t span, int64_t ncurves, int64_t ntiles)
     {
-        const bool need = samples > cap_segid || samples > cap_segtab || ncurves > cap_curves ||
-                          ntiles > cap_tiles || cap_counter < 1 || ncurves > cap_h_curves;
-        if (!need) return hipSuccess;
+        const int64_t bytes = (int64_t)block_bytes(ncurves);
+        if (buf.fits(span, ntiles) && bytes <= cap_dblock && bytes <= cap_hblock && staged)
+            return hipSuccess;
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
-        if ((e = grow(&segid, &cap_segid, samples)) != hipSuccess) return e;
-        if ((e = grow(&segtab, &cap_segtab, samples)) != hipSuccess) return e;
-        if ((e = grow(&curves, &cap_curves, ncurves)) != hipSuccess) return e;
-        if ((e = grow(&tiles, &cap_tiles, ntiles)) != hipSuccess) return e;
-        if ((e = grow(&counter, &cap_counter, 1)) != hipSuccess) return e;
-        if (ncurves > cap_h_curves) {
-            if (h_curves) (void)hipHostFree(h_curves);
-            h_curves = nullptr;
-            cap_h_curves = 0;
-            const int64_t n = std::max<int64_t>(ncurves + ncurves / 4, 256);
-            e = hipHostMalloc(reinterpret_cast<void**>(&h_curves), (size_t)n * sizeof(CurveDesc),
-                              hipHostMallocDefault);
+        staged_pending = false;
+        if ((e = buf.reserve(span, ntiles)) != hipSuccess) return e;
+        if ((e = grow(&dblock, &cap_dblock, bytes)) != hipSuccess) return e;
+        if (bytes > cap_hblock) {
+            if (hblock) (void)hipHostFree(hblock);
+            hblock = nullptr;
+            cap_hblock = 0;
+            const int64_t n = std::max<int64_t>(bytes + bytes / 4, 4096);
+            e = hipHostMalloc(reinterpret_cast<void**>(&hblock), (size_t)n, hipHostMallocDefault);
             if (e != hipSuccess) return e;
-            cap_h_curves = n;
-            staged_pending = false;
+            cap_hblock = n;
         }
-        if (!staged) {
-            e = hipEventCreateWithFlags(&staged, hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        if (!staged) e = hipEventCreateWithFlags(&staged, hipEventDisableTiming);
+        return e;
     }
 };
 
@@ -207,173 +401,107 @@ int cu_count(int device)
     return n;
 }
 
-bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
-
-umi_status check_params(int32_t W, float alpha, float c, int32_t iters)
-{
-    if (W < 1 || (W % 2) == 0)
-        return fail(UMI_ERR_INVALID_ARG, "W must be odd and >= 1 (got " + std::to_string(W) + ")");
-    if (W > UMI_MAX_WINDOW)
-        return fail(UMI_ERR_UNSUPPORTED,
-                    "W=" + std::to_string(W) + " exceeds UMI_MAX_WINDOW=" +
-                        std::to_string(UMI_MAX_WINDOW));
-    if (!finite_pos(alpha)) return fail(UMI_ERR_INVALID_ARG, "alpha must be finite and > 0");
-    if (!finite_pos(c)) return fail(UMI_ERR_INVALID_ARG, "c must be finite and > 0");
-    if (iters < 0) return fail(UMI_ERR_INVALID_ARG, "iters must be >= 0");
-    return UMI_OK;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// direct calls: curves at explicit offsets
 
-umi_status detrend_batch(const float* flux, const double* time, const int64_t* lengths,
-                         int64_t n_curves, const int32_t* W, float alpha, float c, int32_t iters,
-                         float* trend, float* median, const umi_launch* launch,
-                         hipStream_t stream)
+umi_status detrend_gather(const float* flux, const double* time, const int64_t* offsets,
+                          const int64_t* lengths, int64_t n_curves, const int32_t* W,
+                          float alpha, float c, int32_t iters, float* trend, float* median,
+                          const umi_launch* launch, hipStream_t stream)
 {
-    if (t_inject != UMI_OK) {
-        umi_status s = t_inject;
-        t_inject = UMI_OK;
-        return fail(s, "injected error (umi_debug_inject_error)");
-    }
+    umi_status st;
+    if (take_injected(&st)) return st;
     if (n_curves < 0) return fail(UMI_ERR_INVALID_ARG, "n_curves must be >= 0");
     if (n_curves == 0) return UMI_OK;
-    if (!lengths || !W) return fail(UMI_ERR_INVALID_ARG, "lengths and W must not be NULL");
+    if (!offsets || !lengths || !W)
+        return fail(UMI_ERR_INVALID_ARG, "offsets, lengths and W must not be NULL");
     if (n_curves > (int64_t)INT32_MAX) return fail(UMI_ERR_UNSUPPORTED, "too many curves");
-    umi_launch opt = {UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
-    if (launch) opt = *launch;
-    if (opt.reserved != 0) return fail(UMI_ERR_INVALID_ARG, "umi_launch.reserved must be 0");
-    if (opt.mode != UMI_MODE_PERSISTENT && opt.mode != UMI_MODE_PER_CURVE)
-        return fail(UMI_ERR_INVALID_ARG, "unknown launch mode");
-    if (opt.tile < 0 || opt.groups_per_cu < 0)
-        return fail(UMI_ERR_INVALID_ARG, "launch tile and groups_per_cu must be >= 0");
-
-    int64_t total = 0;
-    for (int64_t b = 0; b < n_curves; ++b) {
-        if (lengths[b] < 0) return fail(UMI_ERR_INVALID_ARG, "curve lengths must be >= 0");
-        if (lengths[b] > (int64_t)INT32_MAX)
-            return fail(UMI_ERR_UNSUPPORTED, "a curve longer than 2^31-1 samples");
-        umi_status st = check_params(W[b], alpha, c, iters);
-        if (st != UMI_OK) return st;
-        total += lengths[b];
-    }
+    umi_launch opt;
+    if ((st = check_launch(launch, &opt)) != UMI_OK) return st;
+    if ((st = check_params(alpha, c, iters)) != UMI_OK) return st;
+    int64_t span, total;
+    if ((st = check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK) return st;
     if (total == 0) return UMI_OK;
     if (!flux || !trend) return fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
 
-    // ---- pack: curve table in decreasing per-tile cost, tile bases ----
-    std::vector<int64_t> off((size_t)n_curves);
-    {
-        int64_t acc = 0;
-        for (int64_t b = 0; b < n_curves; ++b) {
-            off[(size_t)b] = acc;
-            acc += lengths[b];
-        }
-    }
-    std::vector<int> tile_of((size_t)n_curves);
-    for (int64_t b = 0; b < n_curves; ++b) {
-        int t, g;
-        tuned(W[b], &t, &g);
-        if (opt.tile > 0) t = std::min(opt.tile, max_tile(W[b]));
-        tile_of[(size_t)b] = t;
-    }
-    std::vector<int32_t> order;
-    order.reserve((size_t)n_curves);
-    for (int64_t b = 0; b < n_curves; ++b)
-        if (lengths[b] > 0) order.push_back((int32_t)b);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const int64_t ca = (int64_t)W[a] * tile_of[(size_t)a];
-        const int64_t cb = (int64_t)W[b] * tile_of[(size_t)b];
-        if (ca != cb) return ca > cb;
-        return lengths[a] > lengths[b];
-    });
-    const int64_t nc = (int64_t)order.size();
-    int64_t ntiles = 0;
-    std::vector<int64_t> curve_tiles((size_t)nc);
-    for (int64_t i = 0; i < nc; ++i) {
-        const int32_t b = order[(size_t)i];
-        curve_tiles[(size_t)i] = (lengths[b] + tile_of[(size_t)b] - 1) / tile_of[(size_t)b];
-        ntiles += curve_tiles[(size_t)i];
-    }
-    if (ntiles > (int64_t)INT32_MAX) return fail(UMI_ERR_UNSUPPORTED, "too many tiles");
-    // persistent grid size: the tuning row of the costliest curve
-    int gpc = kDefaultGroupsPerCU;
-    if (nc > 0) {
-        int t_unused;
-        tuned(W[order[0]], &t_unused, &gpc);
-    }
-    if (opt.groups_per_cu > 0) gpc = opt.groups_per_cu;
+    Packed p;
+    if ((st = pack(offsets, lengths, n_curves, W, opt, &p)) != UMI_OK) return st;
+    const int64_t nc = (int64_t)p.curves.size();
 
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
     Workspace* ws = workspace_for(device, stream);
     std::lock_guard<std::mutex> lk(ws->mu);
-    e = ws->reserve(total, nc, ntiles);
-    if (e != hipSuccess) return fail_hip(e, "workspace allocation");
-
-    // the previous copy out of the staging buffer must be done before reuse
-    if (ws->staged_pending) {
-        e = hipEventSynchronize(ws->staged);
-        if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    if ((e = ws->reserve(span, nc, p.ntiles)) != hipSuccess)
+        return fail_hip(e, "workspace allocation");
+    if (ws->staged_pending) {  // the previous copy out of the staging block must be done
+        if ((e = hipEventSynchronize(ws->staged)) != hipSuccess)
+            return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
-    {
-        int64_t base = 0;
-        for (int64_t i = 0; i < nc; ++i) {
-            const int32_t b = order[(size_t)i];
-            CurveDesc& d = ws->h_curves[i];
-            d.off = off[(size_t)b];
-            d.len = (int32_t)lengths[b];
-            d.W = W[b];
-            d.tile = tile_of[(size_t)b];
-            d.tile_base = (int32_t)base;
-            base += curve_tiles[(size_t)i];
-        }
-    }
-    e = hipMemcpyAsync(ws->curves, ws->h_curves, (size_t)nc * sizeof(CurveDesc),
-                       hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return fail_hip(e, "curve table copy");
-    e = hipEventRecord(ws->staged, stream);
-    if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    write_block(ws->hblock, p, alpha, c, iters);
+    if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
+        return fail_hip(e, "curve table copy");
+    if ((e = hipEventRecord(ws->staged, stream)) != hipSuccess)
+        return fail_hip(e, "hipEventRecord");
     ws->staged_pending = true;
-
-    const int ncu = cu_count(device);
-    if (opt.mode == UMI_MODE_PERSISTENT) {
-        e = launch_prepass(flux, time, ws->curves, 0, (int)nc, ws->segid, ws->segtab, ws->tiles,
-                           ws->counter, stream);
-        if (e != hipSuccess) return fail_hip(e, "pre-pass launch");
-        const int64_t grid = std::min<int64_t>(ntiles, (int64_t)gpc * ncu);
-        if (opt.main_start && (e = hipEventRecord((hipEvent_t)opt.main_start, stream)) != hipSuccess)
-            return fail_hip(e, "hipEventRecord(main_start)");
-        e = launch_main(flux, ws->segid, ws->segtab, ws->curves, ws->tiles, 0, (int)ntiles,
-                        ws->counter, (int)grid, alpha, c, iters, trend, median, stream);
-        if (e != hipSuccess) return fail_hip(e, "main kernel launch");
-        if (opt.main_stop && (e = hipEventRecord((hipEvent_t)opt.main_stop, stream)) != hipSuccess)
-            return fail_hip(e, "hipEventRecord(main_stop)");
-    } else {
-        if (opt.main_start && (e = hipEventRecord((hipEvent_t)opt.main_start, stream)) != hipSuccess)
-            return fail_hip(e, "hipEventRecord(main_start)");
-        int64_t tb = 0;
-        for (int64_t i = 0; i < nc; ++i) {
-            e = launch_prepass(flux, time, ws->curves, (int)i, 1, ws->segid, ws->segtab,
-                               ws->tiles, nullptr, stream);
-            if (e != hipSuccess) return fail_hip(e, "pre-pass launch");
-            const int64_t nt = curve_tiles[(size_t)i];
-            e = launch_main(flux, ws->segid, ws->segtab, ws->curves, ws->tiles, (int)tb,
-                            (int)(tb + nt), nullptr, (int)nt, alpha, c, iters, trend, median,
-                            stream);
-            if (e != hipSuccess) return fail_hip(e, "main kernel launch");
-            tb += nt;
-        }
-        if (opt.main_stop && (e = hipEventRecord((hipEvent_t)opt.main_stop, stream)) != hipSuccess)
-            return fail_hip(e, "hipEventRecord(main_stop)");
-    }
-    // curves of length zero produce nothing; everything else was written
+    const int grid = (int)std::min<int64_t>(p.ntiles, (int64_t)p.gpc * cu_count(device));
+    e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, &p, (int)nc,
+                        grid, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
 
 }  // namespace umi
+
+// ---------------------------------------------------------------------------
+// replayable plans
+
+struct umi_plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t capacity = 0;
+    int64_t max_curves = 0;
+    int64_t max_tiles = 0;
+    int32_t max_W = 0;
+    const float* flux = nullptr;
+    const double* time = nullptr;
+    float* trend = nullptr;
+    float* median = nullptr;
+    int main_grid = 0;
+    umi::DeviceBuffers buf;
+    struct Slot {
+        uint8_t* host = nullptr;    // pinned header + curve table
+        uint8_t* dev = nullptr;     // its device copy
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t done = nullptr;  // recorded after the slot's last replay
+        bool pending = false;
+    } slot[2];
+    int next = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+void plan_free(umi_plan* p)
+{
+    for (auto& s : p->slot) {
+        if (s.exec) (void)hipGraphExecDestroy(s.exec);
+        if (s.graph) (void)hipGraphDestroy(s.graph);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        s = umi_plan::Slot();
+    }
+    p->buf.release();
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -383,14 +511,11 @@ extern "C" {
 umi_status umi_detrend(const float* flux, const double* time, int64_t n, int32_t W, float alpha,
                        float c, int32_t iters, float* trend, float* median, void* stream)
 {
-    if (n < 0) {
-        umi::t_last_error = "n must be >= 0";
-        return UMI_ERR_INVALID_ARG;
-    }
-    const int64_t len = n;
+    if (n < 0) return umi::fail(UMI_ERR_INVALID_ARG, "n must be >= 0");
+    const int64_t off = 0, len = n;
     const int32_t w = W;
-    return umi::detrend_batch(flux, time, &len, 1, &w, alpha, c, iters, trend, median, nullptr,
-                              static_cast<hipStream_t>(stream));
+    return umi::detrend_gather(flux, time, &off, &len, 1, &w, alpha, c, iters, trend, median,
+                               nullptr, static_cast<hipStream_t>(stream));
 }
 
 umi_status umi_detrend_batch(const float* flux, const double* time, const int64_t* lengths,
@@ -398,8 +523,158 @@ umi_status umi_detrend_batch(const float* flux, const double* time, const int64_
                              int32_t iters, float* trend, float* median, const umi_launch* launch,
                              void* stream)
 {
-    return umi::detrend_batch(flux, time, lengths, n_curves, W, alpha, c, iters, trend, median,
-                              launch, static_cast<hipStream_t>(stream));
+    if (n_curves > 0 && !lengths)
+        return umi::fail(UMI_ERR_INVALID_ARG, "lengths must not be NULL");
+    std::vector<int64_t> off(n_curves > 0 ? (size_t)n_curves : 0);
+    int64_t acc = 0;
+    for (int64_t b = 0; b < n_curves; ++b) {
+        off[(size_t)b] = acc;
+        if (lengths[b] > 0) acc += lengths[b];
+    }
+    return umi::detrend_gather(flux, time, off.data(), lengths, n_curves, W, alpha, c, iters,
+                               trend, median, launch, static_cast<hipStream_t>(stream));
+}
+
+umi_status umi_detrend_gather(const float* flux, const double* time, const int64_t* offsets,
+                              const int64_t* lengths, int64_t n_curves, const int32_t* W,
+                              float alpha, float c, int32_t iters, float* trend, float* median,
+                              const umi_launch* launch, void* stream)
+{
+    return umi::detrend_gather(flux, time, offsets, lengths, n_curves, W, alpha, c, iters, trend,
+                               median, launch, static_cast<hipStream_t>(stream));
+}
+
+umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves, int32_t max_W,
+                           const float* flux, const double* time, float* trend, float* median,
+                           void* stream)
+{
+    umi_status st;
+    if (umi::take_injected(&st)) return st;
+    if (!out) return umi::fail(UMI_ERR_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (capacity < 1 || max_curves < 1)
+        return umi::fail(UMI_ERR_INVALID_ARG, "capacity and max_curves must be >= 1");
+    if (max_curves > (1 << 24)) return umi::fail(UMI_ERR_UNSUPPORTED, "max_curves above 2^24");
+    if ((st = umi::check_window(max_W)) != UMI_OK) return st;
+    if (!flux || !trend) return umi::fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
+    if (!stream)
+        return umi::fail(UMI_ERR_INVALID_ARG, "plans need a non-default stream (graph capture)");
+    // the smallest tile any W <= max_W may use, with or without tuning
+    int64_t min_tile = std::min(umi::max_tile(max_W), umi::default_tile(max_W));
+    {
+        std::lock_guard<std::mutex> lk(umi::g_tune_mu);
+        for (const umi::TuneRow& r : umi::g_tune)
+            if (r.tile > 0) min_tile = std::min<int64_t>(min_tile, r.tile);
+    }
+    const int64_t max_tiles = capacity / std::max<int64_t>(1, min_tile) + max_curves;
+    if (max_tiles > (int64_t)INT32_MAX)
+        return umi::fail(UMI_ERR_UNSUPPORTED, "plan capacity needs too many tiles");
+    umi_plan* p = new umi_plan();
+    p->stream = static_cast<hipStream_t>(stream);
+    p->capacity = capacity;
+    p->max_curves = max_curves;
+    p->max_tiles = max_tiles;
+    p->max_W = max_W;
+    p->flux = flux;
+    p->time = time;
+    p->trend = trend;
+    p->median = median;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = p->buf.reserve(capacity, max_tiles);
+    const size_t bytes = umi::block_bytes(max_curves);
+    for (auto& s : p->slot) {
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&s.host), bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s.dev), bytes);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess) std::memset(s.host, 0, bytes);
+    }
+    if (e != hipSuccess) {
+        plan_free(p);
+        delete p;
+        return umi::fail_hip(e, "plan allocation");
+    }
+    int t_unused, gpc;
+    umi::tuned(max_W, &t_unused, &gpc);
+    p->main_grid = gpc * umi::cu_count(p->device);
+    *out = p;
+    return UMI_OK;
+}
+
+umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* lengths,
+                        const int32_t* W, int64_t n_curves, float alpha, float c, int32_t iters)
+{
+    umi_status st;
+    if (umi::take_injected(&st)) return st;
+    if (!p) return umi::fail(UMI_ERR_INVALID_ARG, "plan must not be NULL");
+    if (n_curves < 0 || n_curves > p->max_curves)
+        return umi::fail(UMI_ERR_INVALID_ARG, "n_curves outside [0, max_curves]");
+    if (n_curves > 0 && (!offsets || !lengths || !W))
+        return umi::fail(UMI_ERR_INVALID_ARG, "offsets, lengths and W must not be NULL");
+    if ((st = umi::check_params(alpha, c, iters)) != UMI_OK) return st;
+    int64_t span = 0, total = 0;
+    if (n_curves > 0 &&
+        (st = umi::check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK)
+        return st;
+    if (span > p->capacity)
+        return umi::fail(UMI_ERR_INVALID_ARG, "a curve ends beyond the plan capacity");
+    for (int64_t b = 0; b < n_curves; ++b)
+        if (W[b] > p->max_W) return umi::fail(UMI_ERR_INVALID_ARG, "W above the plan's max_W");
+    const umi_launch opt = {UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
+    umi::Packed pk;
+    if (n_curves > 0 && (st = umi::pack(offsets, lengths, n_curves, W, opt, &pk)) != UMI_OK)
+        return st;
+    if (pk.ntiles > p->max_tiles)
+        return umi::fail(UMI_ERR_UNSUPPORTED, "batch needs more tiles than the plan holds");
+
+    std::lock_guard<std::mutex> lk(p->mu);
+    umi_plan::Slot& s = p->slot[p->next];
+    hipError_t e;
+    if (s.pending) {  // this slot's previous replay must have consumed its bytes
+        if ((e = hipEventSynchronize(s.done)) != hipSuccess)
+            return umi::fail_hip(e, "hipEventSynchronize");
+        s.pending = false;
+    }
+    umi::write_block(s.host, pk, alpha, c, iters);
+    if (!s.exec) {
+        // capture once per slot: copy of the staged block, pre-pass over
+        // max_curves (blocks beyond the batch exit), persistent estimate
+        if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return umi::fail_hip(e, "hipStreamBeginCapture");
+        hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(p->max_curves),
+                                       hipMemcpyHostToDevice, p->stream);
+        if (ce == hipSuccess)
+            ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
+                                      UMI_MODE_PERSISTENT, nullptr, (int)p->max_curves,
+                                      p->main_grid, nullptr, nullptr, p->stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->stream, &g);
+        if (ce != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return umi::fail_hip(ce != hipSuccess ? ce : e, "graph capture");
+        }
+        s.graph = g;
+        if ((e = hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            s.exec = nullptr;
+            return umi::fail_hip(e, "hipGraphInstantiate");
+        }
+    }
+    if ((e = hipGraphLaunch(s.exec, p->stream)) != hipSuccess)
+        return umi::fail_hip(e, "hipGraphLaunch");
+    if ((e = hipEventRecord(s.done, p->stream)) != hipSuccess)
+        return umi::fail_hip(e, "hipEventRecord");
+    s.pending = true;
+    p->next ^= 1;
+    return UMI_OK;
+}
+
+umi_status umi_plan_destroy(umi_plan* p)
+{
+    if (!p) return UMI_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    plan_free(p);
+    delete p;
+    return e == hipSuccess ? UMI_OK : umi::fail_hip(e, "hipStreamSynchronize");
 }
 
 int32_t umi_window_from_cadence(double cadence_days, double window_days)
@@ -426,22 +701,16 @@ umi_status umi_set_tuning(const char* table_text)
             std::istringstream ls(line);
             umi::TuneRow r;
             if (!(ls >> r.w_max >> r.tile >> r.groups_per_cu) || r.w_max < 1 || r.tile < 0 ||
-                r.groups_per_cu < 0 || r.groups_per_cu > 64) {
-                umi::t_last_error = "malformed tuning line: " + line;
-                return UMI_ERR_INVALID_ARG;
-            }
+                r.groups_per_cu < 0 || r.groups_per_cu > 64)
+                return umi::fail(UMI_ERR_INVALID_ARG, "malformed tuning line: " + line);
             std::string extra;
-            if (ls >> extra) {
-                umi::t_last_error = "malformed tuning line: " + line;
-                return UMI_ERR_INVALID_ARG;
-            }
+            if (ls >> extra) return umi::fail(UMI_ERR_INVALID_ARG, "malformed tuning line: " + line);
             rows.push_back(r);
         }
         for (size_t i = 1; i < rows.size(); ++i)
-            if (rows[i].w_max <= rows[i - 1].w_max) {
-                umi::t_last_error = "tuning rows must be sorted by increasing W_max";
-                return UMI_ERR_INVALID_ARG;
-            }
+            if (rows[i].w_max <= rows[i - 1].w_max)
+                return umi::fail(UMI_ERR_INVALID_ARG,
+                                 "tuning rows must be sorted by increasing W_max");
     }
     std::lock_guard<std::mutex> lk(umi::g_tune_mu);
     umi::g_tune = rows;
@@ -466,7 +735,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.1.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.2.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

@@ -17,6 +17,19 @@ constexpr int kPrepItems = 4;                // samples per pre-pass thread per 
 constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1
 constexpr double kGapDays = 0.5;             // segment break threshold (days)
 
+// Per-batch parameters, read by the kernels from device memory so that a
+// captured launch sequence can be replayed for any batch (only the staged
+// bytes change between replays).
+struct BatchHeader {
+    int32_t n_curves;   // entries in the curve table
+    int32_t n_tiles;    // tiles over all curves
+    float alpha;        // asymmetry factor (Eq. 2)
+    float c;            // bisquare tuning constant
+    int32_t iters;      // Phase 3 iterations
+    int32_t pad[3];
+};
+static_assert(sizeof(BatchHeader) == 32, "BatchHeader layout");
+
 // One curve of a packed batch, in the (cost-sorted) order tiles are issued.
 struct CurveDesc {
     int64_t off;        // first sample in the packed arrays

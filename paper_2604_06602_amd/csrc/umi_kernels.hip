@@ -88,7 +88,7 @@ __device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
 
 __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
-    const CurveDesc* __restrict__ curves, int curve_first,
+    const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_first,
     int32_t* __restrict__ segid, int4* __restrict__ segtab,
     int2* __restrict__ tiles, uint32_t* __restrict__ counter)
 {
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
     __shared__ int sh_a[kPrepThreads / 64];
     __shared__ int sh_b[kPrepThreads / 64];
 
-    const int cidx = curve_first + (int)blockIdx.x;
-    const CurveDesc cd = curves[cidx];
     if (counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    const int cidx = curve_first + (int)blockIdx.x;
+    if (cidx >= hdr->n_curves) return;  // fixed-size grids cover fewer curves
+    const CurveDesc cd = curves[cidx];
 
     const int ntiles = cd.len > 0 ? (cd.len + cd.tile - 1) / cd.tile : 0;
     for (int t = threadIdx.x; t < ntiles; t += kPrepThreads)
@@ -397,16 +398,21 @@ __device__ __forceinline__ float upper_ssq(const float* __restrict__ xv, int c0,
 
 __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const float* __restrict__ flux, const int32_t* __restrict__ segid,
-    const int4* __restrict__ segtab, const CurveDesc* __restrict__ curves,
-    const int2* __restrict__ tiles, int tile_first, int tile_end,
-    uint32_t* __restrict__ counter, float alpha, float c, int iters,
-    float* __restrict__ trend, float* __restrict__ median)
+    const int4* __restrict__ segtab, const BatchHeader* __restrict__ hdr,
+    const CurveDesc* __restrict__ curves, const int2* __restrict__ tiles, int tile_first,
+    int tile_count, uint32_t* __restrict__ counter, float* __restrict__ trend,
+    float* __restrict__ median)
 {
     __shared__ MainSmem sm;
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wave = tid >> 6;
     const float nanf_ = __builtin_nanf("");
+    const float alpha = hdr->alpha;
+    const float c = hdr->c;
+    const int iters = hdr->iters;
+    // tile range [tile_first, tile_end): a count < 0 means "all tiles of the batch"
+    const int tile_end = tile_count < 0 ? hdr->n_tiles : tile_first + tile_count;
 
     for (int round = 0;; ++round) {
         if (tid == 0)
@@ -586,25 +592,25 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers (the host library calls only these).
 
-hipError_t launch_prepass(const float* flux, const double* time, const CurveDesc* curves,
-                          int curve_first, int n_curves, int32_t* segid, int4* segtab,
-                          int2* tiles, uint32_t* counter, hipStream_t stream)
+hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
+                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
+                          int4* segtab, int2* tiles, uint32_t* counter, hipStream_t stream)
 {
-    if (n_curves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(umi_prepass_kernel, dim3(n_curves), dim3(kPrepThreads), 0, stream, flux,
-                       time, curves, curve_first, segid, segtab, tiles, counter);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(umi_prepass_kernel, dim3(grid), dim3(kPrepThreads), 0, stream, flux, time,
+                       hdr, curves, curve_first, segid, segtab, tiles, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_main(const float* flux, const int32_t* segid, const int4* segtab,
-                       const CurveDesc* curves, const int2* tiles, int tile_first, int tile_end,
-                       uint32_t* counter, int grid, float alpha, float c, int iters, float* trend,
-                       float* median, hipStream_t stream)
+                       const BatchHeader* hdr, const CurveDesc* curves, const int2* tiles,
+                       int tile_first, int tile_count, uint32_t* counter, int grid,
+                       float* trend, float* median, hipStream_t stream)
 {
-    if (tile_end <= tile_first || grid <= 0) return hipSuccess;
+    if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(umi_main_kernel, dim3(grid), dim3(kMainThreads), 0, stream, flux, segid,
-                       segtab, curves, tiles, tile_first, tile_end, counter, alpha, c, iters,
-                       trend, median);
+                       segtab, hdr, curves, tiles, tile_first, tile_count, counter, trend,
+                       median);
     return hipGetLastError();
 }
 

@@ -1,0 +1,482 @@
+"""Serving loop: continuous batching of detrending requests on one GPU.
+
+Requests (one light curve each) arrive at any time through ``Server.submit``.
+A scheduler thread
+
+  * admits waiting requests first-in first-out while their samples fit the
+    device-memory budget: the budget is one resident arena of device arrays
+    (flux, time, trend) plus the plan's per-sample workspace, and every
+    admission group (the requests admitted together) gets one contiguous
+    range of it, filled by a single host-to-device copy on a copy stream;
+  * launches steps: all admitted, not yet launched groups that share
+    (alpha, c, iters) go into one batch, run through a replayable plan (a
+    captured hipGraph of the tile-table copy, the segmentation pre-pass and
+    the persistent estimate kernel) on the compute stream.  Up to two steps
+    are in flight, so requests that arrive while one step runs are uploaded
+    and staged concurrently and run in the next step;
+  * completes steps: the trend of each group comes back with one
+    device-to-host copy, requests are resolved, and their arena ranges and
+    budget are released.
+
+Latency is measured from the request's arrival time (``submit``'s
+``arrival`` argument, defaulting to now: an open-loop driver passes the
+scheduled arrival) to the moment its result is in host memory.
+
+The executor interface is small so the scheduler can be exercised on the CPU
+with ``FakeExecutor``.
+"""
+from __future__ import annotations
+
+import itertools
+import threading
+import time as _time
+from collections import deque
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Device bytes held per resident sample: flux f32, time f64, trend f32, and
+# the plan workspace (segment id i32 + segment record 4 x i32).
+BYTES_PER_SAMPLE = 4 + 8 + 4 + 4 + 16
+
+
+class Rejected(ValueError):
+    """The request can never be admitted (e.g. larger than the whole budget)."""
+
+
+# ---------------------------------------------------------------------------
+# arena: first-fit allocation of sample ranges
+
+
+class Arena:
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self._free = [(0, self.capacity)]  # sorted, coalesced (start, length)
+        self.used = 0
+        self.high_water = 0
+
+    def alloc(self, n: int):
+        if n <= 0:
+            return 0
+        for i, (s, L) in enumerate(self._free):
+            if L >= n:
+                if L == n:
+                    self._free.pop(i)
+                else:
+                    self._free[i] = (s + n, L - n)
+                self.used += n
+                self.high_water = max(self.high_water, self.used)
+                return s
+        return None
+
+    def free(self, start: int, n: int):
+        if n <= 0:
+            return
+        fl = self._free
+        lo, hi = 0, len(fl)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if fl[mid][0] < start:
+                lo = mid + 1
+            else:
+                hi = mid
+        fl.insert(lo, (start, n))
+        # coalesce with neighbours
+        if lo + 1 < len(fl) and fl[lo][0] + fl[lo][1] == fl[lo + 1][0]:
+            fl[lo] = (fl[lo][0], fl[lo][1] + fl[lo + 1][1])
+            fl.pop(lo + 1)
+        if lo > 0 and fl[lo - 1][0] + fl[lo - 1][1] == fl[lo][0]:
+            fl[lo - 1] = (fl[lo - 1][0], fl[lo - 1][1] + fl[lo][1])
+            fl.pop(lo)
+        self.used -= n
+
+
+# ---------------------------------------------------------------------------
+# requests and groups
+
+
+@dataclass
+class Request:
+    rid: int
+    flux: np.ndarray
+    time: np.ndarray | None
+    W: int
+    alpha: float
+    c: float
+    iters: int
+    arrival: float
+    future: Future
+    admitted: float = 0.0
+    launched: float = 0.0
+    done: float = 0.0
+    offset: int = -1
+
+    @property
+    def n(self) -> int:
+        return int(self.flux.size)
+
+    @property
+    def key(self):
+        return (self.alpha, self.c, self.iters)
+
+
+@dataclass
+class Group:
+    key: tuple
+    offset: int
+    size: int
+    requests: list
+    upload: object = None     # executor token
+    launched: bool = False
+
+
+@dataclass
+class Step:
+    groups: list
+    handle: object = None
+    launched_at: float = 0.0
+
+
+@dataclass
+class Stats:
+    latencies: list = field(default_factory=list)
+    completed: int = 0
+    failed: int = 0
+    rejected: int = 0
+    steps: int = 0
+    samples: int = 0
+    first_arrival: float | None = None
+    last_done: float | None = None
+
+    def summary(self, arena: Arena | None = None) -> dict:
+        lat = np.array(self.latencies) if self.latencies else np.zeros(0)
+        span = (self.last_done - self.first_arrival) if self.completed else 0.0
+        out = {
+            "completed": self.completed, "failed": self.failed, "rejected": self.rejected,
+            "steps": self.steps,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "max_ms": float(lat.max() * 1e3) if lat.size else None,
+            "curves_per_s": self.completed / span if span > 0 else None,
+            "samples_per_s": self.samples / span if span > 0 else None,
+        }
+        if arena is not None:
+            out["arena_high_water_samples"] = arena.high_water
+            out["arena_capacity_samples"] = arena.capacity
+        return out
+
+
+# ---------------------------------------------------------------------------
+# executors
+
+
+class GpuExecutor:
+    """Resident device arrays, a copy stream and a compute stream, and a
+    replayable plan over the arrays."""
+
+    def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device=0):
+        import torch
+
+        from . import _lib
+        self.torch = torch
+        self.capacity = int(capacity)
+        self.dev = torch.device("cuda", device)
+        self.flux = torch.zeros(self.capacity, dtype=torch.float32, device=self.dev)
+        self.time = torch.zeros(self.capacity, dtype=torch.float64, device=self.dev)
+        self.trend = torch.zeros(self.capacity, dtype=torch.float32, device=self.dev)
+        self.copy_stream = torch.cuda.Stream(device=self.dev)
+        self.compute_stream = torch.cuda.Stream(device=self.dev)
+        self.plan = _lib.Plan(self.flux, self.time, self.trend, None, max_curves=max_curves,
+                              max_W=max_W, stream=self.compute_stream)
+        self.max_curves = int(max_curves)
+        self.max_W = int(max_W)
+
+    def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
+        torch = self.torch
+        hf = torch.from_numpy(flux).pin_memory()
+        ht = torch.from_numpy(time).pin_memory()
+        with torch.cuda.stream(self.copy_stream):
+            self.flux[offset:offset + flux.size].copy_(hf, non_blocking=True)
+            self.time[offset:offset + flux.size].copy_(ht, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        return (ev, hf, ht)  # the pinned buffers live until the group completes
+
+    def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+        """Run one batch; then copy each (offset, size) range of the trend back."""
+        torch = self.torch
+        for ev, _, _ in uploads:
+            self.compute_stream.wait_event(ev)
+        alpha, c, iters = key
+        self.plan.run(offsets, lengths, Ws, alpha, c, iters)
+        computed = torch.cuda.Event()
+        computed.record(self.compute_stream)
+        outs = []
+        with torch.cuda.stream(self.copy_stream):
+            self.copy_stream.wait_event(computed)
+            for off, size in ranges:
+                h = torch.empty(size, dtype=torch.float32, pin_memory=True)
+                h.copy_(self.trend[off:off + size], non_blocking=True)
+                outs.append(h)
+            done = torch.cuda.Event()
+            done.record(self.copy_stream)
+        return (done, outs)
+
+    def ready(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle):
+        handle[0].synchronize()
+        return [h.numpy() for h in handle[1]]
+
+    def close(self):
+        self.plan.destroy()
+
+
+class FakeExecutor:
+    """CPU stand-in with the executor interface: `fn(flux, time, W, alpha, c,
+    iters)` computes one curve, `delay` seconds model a step's device time,
+    and `fail_when(step_index, curves)` may raise to inject a step failure."""
+
+    def __init__(self, capacity: int, fn=None, delay: float = 0.0, fail_when=None,
+                 max_curves: int = 4096):
+        self.capacity = int(capacity)
+        self.flux = np.zeros(self.capacity, np.float32)
+        self.time = np.zeros(self.capacity, np.float64)
+        self.fn = fn or (lambda f, t, W, a, c, it: f.astype(np.float32) * np.float32(2.0))
+        self.delay = delay
+        self.fail_when = fail_when
+        self.max_curves = int(max_curves)
+        self.max_W = 2047
+        self._step = itertools.count()
+
+    def upload(self, offset, flux, time):
+        self.flux[offset:offset + flux.size] = flux
+        self.time[offset:offset + flux.size] = time
+        return None
+
+    def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+        k = next(self._step)
+        if self.fail_when is not None:
+            self.fail_when(k, len(offsets))
+        alpha, c, iters = key
+        trend = np.full(self.capacity, np.nan, np.float32)
+        for o, L, W in zip(offsets, lengths, Ws):
+            trend[o:o + L] = self.fn(self.flux[o:o + L], self.time[o:o + L], W, alpha, c, iters)
+        outs = [trend[o:o + s].copy() for o, s in ranges]
+        return (_time.perf_counter() + self.delay, outs)
+
+    def ready(self, handle) -> bool:
+        return _time.perf_counter() >= handle[0]
+
+    def results(self, handle):
+        while not self.ready(handle):
+            _time.sleep(max(0.0, handle[0] - _time.perf_counter()))
+        return handle[1]
+
+    def close(self):
+        pass
+
+
+# ---------------------------------------------------------------------------
+# server
+
+
+class Server:
+    def __init__(self, executor, max_step_curves: int | None = None, max_inflight: int = 2,
+                 clock=_time.perf_counter):
+        self.ex = executor
+        self.arena = Arena(executor.capacity)
+        self.max_step_curves = int(max_step_curves or getattr(executor, "max_curves", 4096))
+        self.max_inflight = max_inflight
+        self.max_W = int(getattr(executor, "max_W", 2047))
+        self.clock = clock
+        self.stats = Stats()
+        self._ids = itertools.count()
+        self._lock = threading.Condition()
+        self._waiting: deque = deque()   # submitted, not admitted
+        self._groups: list = []           # admitted, not launched
+        self._inflight: deque = deque()   # launched steps, oldest first
+        self._closing = False
+        self._error: BaseException | None = None
+        self._thread = threading.Thread(target=self._loop, name="umi-serve", daemon=True)
+        self._thread.start()
+
+    # -- client side -------------------------------------------------------
+    def submit(self, flux, time=None, W: int = 361, alpha: float = 2.0, c: float = 5.0,
+               iters: int = 5, arrival: float | None = None) -> Future:
+        fut: Future = Future()
+        flux = np.ascontiguousarray(flux, dtype=np.float32)
+        if time is None:
+            time_ = np.zeros(flux.size, np.float64)  # no gap information
+        else:
+            time_ = np.ascontiguousarray(time, dtype=np.float64)
+        arrival = self.clock() if arrival is None else arrival
+        try:
+            if flux.ndim != 1 or time_.shape != flux.shape:
+                raise ValueError("flux and time must be 1-D of equal length")
+            if W < 1 or W % 2 == 0 or W > self.max_W:
+                raise ValueError("W must be odd, 1 <= W <= %d" % self.max_W)
+            if not (alpha > 0 and c > 0 and iters >= 0):
+                raise ValueError("need alpha > 0, c > 0, iters >= 0")
+            if flux.size > self.arena.capacity:
+                raise Rejected("curve of %d samples exceeds the device budget of %d samples"
+                               % (flux.size, self.arena.capacity))
+        except ValueError as e:
+            with self._lock:
+                self.stats.rejected += 1
+            fut.set_exception(e)
+            return fut
+        req = Request(next(self._ids), flux, time_, int(W), float(alpha), float(c), int(iters),
+                      arrival, fut)
+        with self._lock:
+            if self._closing:
+                raise RuntimeError("server is closed")
+            if self.stats.first_arrival is None or arrival < self.stats.first_arrival:
+                self.stats.first_arrival = arrival
+            self._waiting.append(req)
+            self._lock.notify_all()
+        return fut
+
+    def close(self, timeout: float | None = None):
+        """Finish everything submitted, then stop."""
+        with self._lock:
+            self._closing = True
+            self._lock.notify_all()
+        self._thread.join(timeout)
+        self.ex.close()
+        if self._error is not None:
+            raise RuntimeError("scheduler failed") from self._error
+
+    def summary(self) -> dict:
+        with self._lock:
+            return self.stats.summary(self.arena)
+
+    # -- scheduler ---------------------------------------------------------
+    def _admit(self):
+        """Admit waiting requests FIFO into contiguous arena groups per key."""
+        admitted = []
+        while self._waiting:
+            req = self._waiting[0]
+            if req.future.cancelled():
+                self._waiting.popleft()
+                continue
+            off = self.arena.alloc(req.n)
+            if off is None:
+                break  # head of line waits for memory: FIFO admission
+            self._waiting.popleft()
+            req.offset = off
+            req.admitted = self.clock()
+            admitted.append(req)
+        # requests admitted together with equal parameters form one group; a
+        # group's arena range is contiguous when its requests' ranges are
+        groups = []
+        for req in admitted:
+            g = groups[-1] if groups else None
+            if g is not None and g.key == req.key and g.offset + g.size == req.offset:
+                g.requests.append(req)
+                g.size += req.n
+            else:
+                groups.append(Group(req.key, req.offset, req.n, [req]))
+        return groups
+
+    def _upload(self, groups):
+        for g in groups:
+            flux = np.concatenate([r.flux for r in g.requests]) if len(g.requests) > 1 else g.requests[0].flux
+            tim = np.concatenate([r.time for r in g.requests]) if len(g.requests) > 1 else g.requests[0].time
+            g.upload = self.ex.upload(g.offset, flux, tim)
+
+    def _next_step(self):
+        """The oldest admitted key's groups, up to the step's curve limit."""
+        if not self._groups:
+            return None
+        key = self._groups[0].key
+        chosen, n = [], 0
+        for g in self._groups:
+            if g.key == key and n + len(g.requests) <= self.max_step_curves:
+                chosen.append(g)
+                n += len(g.requests)
+            elif g.key == key and not chosen:
+                chosen.append(g)  # a group is never split
+                break
+        for g in chosen:
+            self._groups.remove(g)
+        return Step(chosen)
+
+    def _launch(self, step: Step):
+        reqs = [r for g in step.groups for r in g.requests]
+        now = self.clock()
+        for r in reqs:
+            r.launched = now
+        try:
+            step.handle = self.ex.launch([r.offset for r in reqs], [r.n for r in reqs],
+                                         [r.W for r in reqs], step.groups[0].key,
+                                         [g.upload for g in step.groups if g.upload is not None],
+                                         [(g.offset, g.size) for g in step.groups])
+            step.launched_at = now
+            self.stats.steps += 1
+            return True
+        except Exception as e:  # a failed step fails only its own requests
+            self._finish(step, error=e)
+            return False
+
+    def _finish(self, step: Step, error: BaseException | None = None):
+        outs = None
+        if error is None:
+            try:
+                outs = self.ex.results(step.handle)
+            except Exception as e:
+                error = e
+        now = self.clock()
+        for gi, g in enumerate(step.groups):
+            pos = 0
+            for r in g.requests:
+                r.done = now
+                if error is None:
+                    res = outs[gi][pos:pos + r.n]
+                    if not r.future.cancelled():
+                        r.future.set_result(res)
+                    self.stats.completed += 1
+                    self.stats.samples += r.n
+                    self.stats.latencies.append(now - r.arrival)
+                else:
+                    if not r.future.cancelled():
+                        r.future.set_exception(error)
+                    self.stats.failed += 1
+                pos += r.n
+            self.arena.free(g.offset, g.size)
+        self.stats.last_done = now
+
+    def _loop(self):
+        try:
+            while True:
+                with self._lock:
+                    # completions first: they free memory for admissions
+                    while self._inflight and self.ex.ready(self._inflight[0].handle):
+                        self._finish(self._inflight.popleft())
+                    groups = self._admit()
+                self._upload(groups)
+                with self._lock:
+                    self._groups.extend(groups)
+                    while self._groups and len(self._inflight) < self.max_inflight:
+                        step = self._next_step()
+                        if self._launch(step):
+                            self._inflight.append(step)
+                    idle = not self._inflight and not self._groups
+                    if idle and not self._waiting and self._closing:
+                        return
+                    if idle and not self._waiting:
+                        self._lock.wait(0.05)
+                    elif self._inflight:
+                        # poll the oldest step without holding the lock long
+                        pass
+                if self._inflight:
+                    _time.sleep(2e-5)
+        except BaseException as e:  # keep the failure visible to close()
+            self._error = e
+            with self._lock:
+                for r in list(self._waiting):
+                    if not r.future.done():
+                        r.future.set_exception(RuntimeError("scheduler failed: %r" % e))
+                self._waiting.clear()

@@ -119,3 +119,61 @@ def test_tuning_table_parsing(lib):
         with pytest.raises(lib.UmiError):
             lib.set_tuning(bad)
     lib.set_tuning(None)
+
+
+def test_gather_validation_without_device(lib):
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+
+    def gather(offs, lens, Ws):
+        o = np.asarray(offs, np.int64)
+        L = np.asarray(lens, np.int64)
+        w = np.asarray(Ws, np.int32)
+        return lib.lib.umi_detrend_gather(ctypes.c_void_p(1), None, o.ctypes.data_as(i64),
+                                          L.ctypes.data_as(i64), L.size, w.ctypes.data_as(i32),
+                                          2.0, 5.0, 5, ctypes.c_void_p(1), None, None, None)
+    assert gather([0, 50], [100, 100], [5, 5]) == 1          # overlapping ranges
+    assert gather([-1], [10], [5]) == 1                      # negative offset
+    assert gather([0, 100], [100, 0], [5, 4]) == 1           # even W even on an empty curve
+    assert gather([0, 100], [0, 0], [5, 5]) == 0             # nothing to do
+    assert lib.lib.umi_detrend_gather(None, None, None, None, 0, None, 2.0, 5.0, 5, None, None,
+                                      None, None) == 0
+
+
+def test_plan_validation_without_device(lib):
+    h = ctypes.c_void_p()
+    # no stream: graph capture needs a non-default stream
+    assert lib.lib.umi_plan_create(ctypes.byref(h), 100, 4, 25, ctypes.c_void_p(1), None,
+                                   ctypes.c_void_p(1), None, None) == 1
+    assert lib.lib.umi_plan_create(ctypes.byref(h), 0, 4, 25, ctypes.c_void_p(1), None,
+                                   ctypes.c_void_p(1), None, ctypes.c_void_p(1)) == 1
+    assert lib.lib.umi_plan_create(ctypes.byref(h), 100, 4, 24, ctypes.c_void_p(1), None,
+                                   ctypes.c_void_p(1), None, ctypes.c_void_p(1)) == 1
+    assert lib.lib.umi_plan_create(None, 100, 4, 25, ctypes.c_void_p(1), None,
+                                   ctypes.c_void_p(1), None, ctypes.c_void_p(1)) == 1
+    assert lib.lib.umi_plan_run(None, None, None, None, 0, 2.0, 5.0, 5) == 1
+    assert lib.lib.umi_plan_destroy(None) == 0
+
+
+def test_autotune_table_is_loadable(lib, monkeypatch):
+    from paper_2604_06602_amd import autotune
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+    table = autotune.load_table()
+    assert table is not None, "no committed tuning table for this library version"
+    lib.set_tuning(table)          # the library accepts it
+    lib.set_tuning(None)
+    rows = [tuple(map(int, l.split())) for l in table.strip().splitlines()]
+    assert [r[0] for r in rows] == [b[0] for b in autotune.BUCKETS]
+    for w_max, tile, gpc in rows:
+        assert 1 <= tile <= autotune.max_tile(w_max) or tile <= autotune.max_tile(
+            dict(autotune.BUCKETS)[w_max])
+        assert 1 <= gpc <= 4
+
+
+def test_autotune_candidates():
+    from paper_2604_06602_amd import autotune
+    assert autotune.default_tile(361) == 1536 and autotune.default_tile(25) == 2024
+    assert autotune.default_tile(721) == 1328 and autotune.default_tile(2047) == 2
+    for W in [25, 121, 361, 721, 1441]:
+        c = autotune.tile_candidates(W)
+        assert autotune.default_tile(W) in c and max(c) == autotune.max_tile(W)

@@ -1,0 +1,187 @@
+"""Serving scheduler on the CPU: a fake executor stands in for the GPU.
+
+Covers the arena allocator, continuous batching (results identical alone and
+in a mix), admission by budget, rejection, cancellation, a failed step
+failing only its own requests, and parameter grouping.
+"""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+from paper_2604_06602_amd.serve import Arena, FakeExecutor, Rejected, Server
+
+
+def running_mean(f, t, W, a, c, it):
+    k = np.ones(W) / W
+    return (np.convolve(f.astype(np.float64), k, mode="same") * a + c + it).astype(np.float32)
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.tuples(st.booleans(), st.integers(1, 40)), max_size=60))
+def test_arena_matches_a_bitmap(ops):
+    cap = 200
+    a = Arena(cap)
+    used = np.zeros(cap, bool)
+    live = []
+    for is_alloc, n in ops:
+        if is_alloc or not live:
+            off = a.alloc(n)
+            if off is None:
+                # first fit failed: no run of n free slots may exist
+                assert all(r < n for r in _free_runs(used))
+                continue
+            assert not used[off:off + n].any() and off + n <= cap
+            used[off:off + n] = True
+            live.append((off, n))
+        else:
+            off, n = live.pop(len(live) // 2)
+            a.free(off, n)
+            used[off:off + n] = False
+        assert a.used == used.sum()
+        # free list is sorted, disjoint, coalesced, and matches the bitmap
+        prev_end = -1
+        for s, L in a._free:
+            assert s > prev_end and not used[s:s + L].any()
+            prev_end = s + L
+        assert sum(L for _, L in a._free) == cap - used.sum()
+
+
+def _free_runs(used):
+    runs, n = [], 0
+    for u in used:
+        if u:
+            if n:
+                runs.append(n)
+            n = 0
+        else:
+            n += 1
+    if n:
+        runs.append(n)
+    return runs
+
+
+def _curves(n, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        L = int(rng.integers(50, 400))
+        out.append((rng.normal(1, 1e-3, L).astype(np.float32), np.arange(L) * 0.01,
+                    int(rng.choice([5, 11, 25]))))
+    return out
+
+
+def test_results_identical_alone_and_in_a_mix():
+    curves = _curves(40)
+    alone = []
+    srv = Server(FakeExecutor(100000, fn=running_mean))
+    for f, t, W in curves:
+        alone.append(srv.submit(f, t, W).result(timeout=10))
+    srv.close()
+    srv = Server(FakeExecutor(100000, fn=running_mean, delay=0.002))
+    futs = [srv.submit(f, t, W) for f, t, W in curves]
+    mixed = [fu.result(timeout=10) for fu in futs]
+    s = srv.summary()
+    srv.close()
+    for x, y in zip(alone, mixed):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert s["completed"] == 40 and s["steps"] < 40  # requests shared steps
+
+
+def test_budget_forces_queueing_and_everything_completes():
+    curves = [(np.ones(400, np.float32), None, 5) for _ in range(30)]
+    ex = FakeExecutor(1000, delay=0.001)
+    srv = Server(ex)
+    futs = [srv.submit(f, t, W) for f, t, W in curves]
+    for fu in futs:
+        assert np.array_equal(fu.result(timeout=10), np.full(400, 2.0, np.float32))
+    s = srv.summary()
+    srv.close()
+    assert s["arena_high_water_samples"] <= 1000 and s["completed"] == 30
+
+
+def test_oversize_and_invalid_requests_are_rejected():
+    srv = Server(FakeExecutor(1000))
+    with pytest.raises(Rejected):
+        srv.submit(np.ones(1001, np.float32)).result(timeout=5)
+    with pytest.raises(ValueError):
+        srv.submit(np.ones(10, np.float32), W=4).result(timeout=5)
+    with pytest.raises(ValueError):
+        srv.submit(np.ones(10, np.float32), alpha=0.0).result(timeout=5)
+    ok = srv.submit(np.ones(1000, np.float32), W=5)
+    assert ok.result(timeout=5).size == 1000
+    s = srv.summary()
+    srv.close()
+    assert s["rejected"] == 3
+
+
+def test_cancelled_request_never_runs():
+    gate = threading.Event()
+
+    def slow(f, t, W, a, c, it):
+        gate.wait(5)
+        return f.copy()
+    srv = Server(FakeExecutor(500, fn=slow))
+    first = srv.submit(np.ones(500, np.float32), W=5)   # fills the whole budget
+    time.sleep(0.05)
+    second = srv.submit(np.ones(100, np.float32), W=5)  # must wait for memory
+    assert second.cancel()
+    gate.set()
+    first.result(timeout=5)
+    srv.close()
+    assert second.cancelled()
+    assert srv.summary()["completed"] == 1
+
+
+def test_failed_step_fails_only_its_requests():
+    def fail_second(step, n):
+        if step == 1:
+            raise RuntimeError("injected device fault")
+    ex = FakeExecutor(100000, delay=0.01, fail_when=fail_second)
+    srv = Server(ex, max_inflight=1)
+    a = srv.submit(np.ones(100, np.float32), W=5)
+    a.result(timeout=5)
+    b = srv.submit(np.ones(100, np.float32), W=5)
+    with pytest.raises(RuntimeError, match="injected"):
+        b.result(timeout=5)
+    c = srv.submit(np.ones(100, np.float32), W=5)
+    assert c.result(timeout=5)[0] == 2.0
+    s = srv.summary()
+    srv.close()
+    assert s["failed"] == 1 and s["completed"] == 2
+
+
+def test_parameters_never_share_a_step():
+    seen = []
+
+    def record(f, t, W, a, c, it):
+        seen.append((a, c, it))
+        return f.copy()
+
+    class Recording(FakeExecutor):
+        def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+            steps.append(key)
+            return super().launch(offsets, lengths, Ws, key, uploads, ranges)
+    steps = []
+    srv = Server(Recording(100000, fn=record, delay=0.005))
+    futs = [srv.submit(np.ones(50, np.float32), W=5, alpha=a) for a in [2.0, 1.0, 2.0, 1.0, 10.0]]
+    for fu in futs:
+        fu.result(timeout=5)
+    srv.close()
+    assert sorted(set(seen)) == sorted(set((a, 5.0, 5) for a in [2.0, 1.0, 10.0]))
+    assert len(steps) >= 3
+
+
+def test_latency_is_measured_from_scheduled_arrival():
+    srv = Server(FakeExecutor(10000, delay=0.01))
+    t0 = time.perf_counter()
+    fu = srv.submit(np.ones(10, np.float32), W=5, arrival=t0 - 0.5)
+    fu.result(timeout=5)
+    s = srv.summary()
+    srv.close()
+    assert s["p50_ms"] >= 500
