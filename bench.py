@@ -110,6 +110,54 @@ def counted_traffic():
         return None
 
 
+SERVE_POOL = 1000  # distinct curves drawn like the mixed workload, cycled by arrivals
+
+
+def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=50):
+    """Open-loop serving: Poisson arrivals (rate curves/s) of curves drawn like
+    the mixed workload, device-memory budget `budget_gb`; latency from the
+    scheduled arrival to the result in host memory."""
+    import synth
+    from paper_2604_06602_amd.serve import BYTES_PER_SAMPLE, GpuExecutor, Server, run_open_loop
+    log("drawing %d serving curves" % SERVE_POOL)
+    pool = [synth.curve_for(4, i) for i in range(SERVE_POOL)]
+    capacity = int(budget_gb * 1e9) // BYTES_PER_SAMPLE
+    results = []
+    ex = GpuExecutor(capacity, max_curves=4096, max_W=721)
+    srv = Server(ex)
+    for i in range(8):  # warm up: capture both graph slots, touch the pinned pool
+        srv.submit(*pool[i]).result()
+    for rate in rates:
+        arrivals = synth.poisson_arrivals(rate, seconds, seed=int(rate))
+        srv.reset_stats()
+        keep = (lambda i: i % oracle_every == 0) if check_oracle else None
+        summary, kept = run_open_loop(srv, pool, arrivals, keep)
+        entry = {"rate_curves_per_s": rate, "seconds": seconds, "requests": int(arrivals.size),
+                 "budget_gb": budget_gb, **summary}
+        if check_oracle and kept:
+            import oracle
+            oracle.build(force=False)
+            rng = np.random.default_rng(0)
+            worst = 0.0
+            for i, (ci, res) in kept.items():
+                f, t, W = pool[ci]
+                idx = np.unique(rng.integers(0, f.size, 64))
+                o_tr, _ = oracle.detrend_at(f, t, W, idx)
+                ok = ~np.isnan(o_tr)
+                if ok.any():
+                    worst = max(worst, float(np.max(np.abs(res[idx][ok] - o_tr[ok]) / np.abs(o_tr[ok]))))
+            entry["oracle_checked_requests"] = len(kept)
+            entry["max_rel_err_vs_fp64_oracle"] = worst
+        log("rate %g/s: p50 %.2f ms, p99 %.2f ms, %.0f curves/s, %d steps"
+            % (rate, entry["p50_ms"] or -1, entry["p99_ms"] or -1, entry["curves_per_s"] or -1,
+               entry["steps"]))
+        results.append(entry)
+    srv.close()
+    del ex, srv
+    return {"metric": "serving latency (open-loop Poisson arrivals, mixed curves)",
+            "unit": "ms", "rates": results}
+
+
 def batch_prefix(batch, n):
     import synth
     return synth.lightcurves.pack([batch.curve(i) for i in range(n)])
@@ -132,6 +180,14 @@ def main(argv=None):
                          "(built-in defaults) or a table file")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving sweep instead: open-loop Poisson arrivals of mixed curves "
+                         "at each --rates value (curves/s) for --serve-seconds each")
+    ap.add_argument("--rates", default="100,300,1000,3000,10000,20000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--no-serve-leg", action="store_true",
+                    help="skip the short serving measurement of the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (to scale "
                          "HBM byte counters) and exit")
@@ -159,6 +215,13 @@ def main(argv=None):
 
     def log(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    if args.serve:
+        rates = [float(r) for r in args.rates.split(",")]
+        out = serve_sweep(rates, args.serve_seconds, args.budget_gb, log,
+                          check_oracle=not args.no_cpu_baseline)
+        print(json.dumps(out), flush=True)
+        return 0
 
     log("generating workload %d" % args.workload)
     batch = synth.config_batch(args.workload)
@@ -283,6 +346,11 @@ def main(argv=None):
         out["comparison"] = per_curve
     if args.workload != 1:
         out["roofline"]["traffic"] = None  # the committed counters cover workload 1 only
+    if not args.no_serve_leg:
+        log("serving leg: 2000 curves/s for 3 s")
+        del flux, tim, trend
+        torch.cuda.empty_cache()
+        out["serve"] = serve_sweep([2000.0], 3.0, args.budget_gb, log, check_oracle=False)["rates"][0]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)

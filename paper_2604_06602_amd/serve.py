@@ -96,7 +96,7 @@ class Arena:
 # requests and groups
 
 
-@dataclass
+@dataclass(slots=True)
 class Request:
     rid: int
     flux: np.ndarray
@@ -141,6 +141,14 @@ class Step:
 @dataclass
 class Stats:
     latencies: list = field(default_factory=list)
+    queued: list = field(default_factory=list)     # arrival -> admitted
+    staged: list = field(default_factory=list)     # admitted -> launched
+    service: list = field(default_factory=list)    # launched -> result in host memory
+    step_curves: list = field(default_factory=list)
+    loop_max_s: float = 0.0                          # longest scheduler iteration
+    phase_s: dict = field(default_factory=lambda: {"finish": 0.0, "admit": 0.0,
+                                                   "upload": 0.0, "launch": 0.0})
+    submit_lag: list = field(default_factory=list)  # arrival -> submit() called
     completed: int = 0
     failed: int = 0
     rejected: int = 0
@@ -161,6 +169,16 @@ class Stats:
             "curves_per_s": self.completed / span if span > 0 else None,
             "samples_per_s": self.samples / span if span > 0 else None,
         }
+        for name in ("queued", "staged", "service"):
+            v = np.array(getattr(self, name)) if getattr(self, name) else np.zeros(0)
+            out[name + "_p50_ms"] = float(np.percentile(v, 50) * 1e3) if v.size else None
+            out[name + "_p99_ms"] = float(np.percentile(v, 99) * 1e3) if v.size else None
+        sc = np.array(self.step_curves) if self.step_curves else np.zeros(0)
+        out["mean_curves_per_step"] = float(sc.mean()) if sc.size else None
+        lag = np.array(self.submit_lag) if self.submit_lag else np.zeros(0)
+        out["submit_lag_p99_ms"] = float(np.percentile(lag, 99) * 1e3) if lag.size else None
+        out["scheduler_longest_iteration_ms"] = self.loop_max_s * 1e3
+        out["scheduler_phase_s"] = dict(self.phase_s)
         if arena is not None:
             out["arena_high_water_samples"] = arena.high_water
             out["arena_capacity_samples"] = arena.capacity
@@ -171,11 +189,64 @@ class Stats:
 # executors
 
 
-class GpuExecutor:
-    """Resident device arrays, a copy stream and a compute stream, and a
-    replayable plan over the arrays."""
+class PinnedRing:
+    """A preallocated pinned host buffer handed out as a ring: blocks are
+    allocated at the head and released in any order; space comes back when
+    the oldest live blocks are released.  Avoids pinned allocations (which
+    are slow and can serialise with the device) on the serving path."""
 
-    def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device=0):
+    ALIGN = 256
+
+    def __init__(self, torch, nbytes: int):
+        self.buf = torch.empty(int(nbytes), dtype=torch.uint8, pin_memory=True)
+        self.mem = self.buf.numpy()
+        self.size = int(nbytes)
+        self.head = 0
+        self.live = deque()  # [start, end, released] oldest first
+
+    def _reclaim(self):
+        while self.live and self.live[0][2]:
+            self.live.popleft()
+
+    def alloc(self, nbytes: int):
+        """A block of at least nbytes, as (token, start), or None if full."""
+        n = -(-int(nbytes) // self.ALIGN) * self.ALIGN
+        if n > self.size:
+            return None
+        self._reclaim()
+        tail = self.live[0][0] if self.live else None
+        start = self.head
+        if tail is None:
+            start = 0 if self.head + n > self.size else self.head
+        elif self.head >= tail:           # free space: [head, size) and [0, tail)
+            if self.head + n > self.size:
+                if n >= tail:
+                    return None
+                start = 0
+        elif self.head + n >= tail:       # free space: [head, tail)
+            return None
+        blk = [start, start + n, False]
+        self.live.append(blk)
+        self.head = start + n
+        return blk, start
+
+    def release(self, token):
+        token[2] = True
+        self._reclaim()
+
+    def view(self, start: int, dtype, count: int):
+        return self.mem[start:start + count * np.dtype(dtype).itemsize].view(dtype)
+
+    def tensor(self, start: int, torch_dtype, count: int, itemsize: int):
+        return self.buf[start:start + count * itemsize].view(torch_dtype)
+
+
+class GpuExecutor:
+    """Resident device arrays, a copy stream and a compute stream, pinned
+    staging rings, and a replayable plan over the arrays."""
+
+    def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device=0,
+                 staging_bytes: int = 4 << 30):
         import torch
 
         from . import _lib
@@ -191,17 +262,41 @@ class GpuExecutor:
                               max_W=max_W, stream=self.compute_stream)
         self.max_curves = int(max_curves)
         self.max_W = int(max_W)
+        self.ring_in = PinnedRing(torch, staging_bytes)        # flux + time of admitted groups
+        self.ring_out = PinnedRing(torch, staging_bytes // 3)  # trend of finished steps
 
-    def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
+    def _pinned(self, ring, nbytes):
+        got = ring.alloc(nbytes)
+        if got is None:  # ring full: a one-off pinned block
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, pin_memory=True)
+            return None, t, t.numpy()
+        tok, start = got
+        return tok, ring.buf[start:start + int(nbytes)], ring.mem[start:start + int(nbytes)]
+
+    def stage_upload(self, offset: int, parts):
+        """Copy the group's curves ((flux, time) pairs) into pinned staging and
+        start one host-to-device copy per array on the copy stream."""
         torch = self.torch
-        hf = torch.from_numpy(flux).pin_memory()
-        ht = torch.from_numpy(time).pin_memory()
+        n = sum(f.size for f, _ in parts)
+        tok, tbuf, mem = self._pinned(self.ring_in, 12 * n)
+        # layout: time first (8-byte aligned), then flux
+        tview = mem[:8 * n].view(np.float64)
+        fview = mem[8 * n:12 * n].view(np.float32)
+        pos = 0
+        for f, t in parts:
+            fview[pos:pos + f.size] = f
+            tview[pos:pos + f.size] = t
+            pos += f.size
         with torch.cuda.stream(self.copy_stream):
-            self.flux[offset:offset + flux.size].copy_(hf, non_blocking=True)
-            self.time[offset:offset + flux.size].copy_(ht, non_blocking=True)
+            self.time[offset:offset + n].copy_(tbuf[:8 * n].view(torch.float64), non_blocking=True)
+            self.flux[offset:offset + n].copy_(tbuf[8 * n:12 * n].view(torch.float32),
+                                               non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.copy_stream)
-        return (ev, hf, ht)  # the pinned buffers live until the group completes
+        return (ev, tok, tbuf)
+
+    def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
+        return self.stage_upload(offset, [(flux, time)])
 
     def launch(self, offsets, lengths, Ws, key, uploads, ranges):
         """Run one batch; then copy each (offset, size) range of the trend back."""
@@ -209,26 +304,43 @@ class GpuExecutor:
         for ev, _, _ in uploads:
             self.compute_stream.wait_event(ev)
         alpha, c, iters = key
-        self.plan.run(offsets, lengths, Ws, alpha, c, iters)
+        try:
+            self.plan.run(offsets, lengths, Ws, alpha, c, iters)
+        except Exception:
+            # the step never ran: its uploads' staging is free once copied
+            for ev, tok, _ in uploads:
+                ev.synchronize()
+                if tok is not None:
+                    self.ring_in.release(tok)
+            raise
         computed = torch.cuda.Event()
         computed.record(self.compute_stream)
         outs = []
         with torch.cuda.stream(self.copy_stream):
             self.copy_stream.wait_event(computed)
             for off, size in ranges:
-                h = torch.empty(size, dtype=torch.float32, pin_memory=True)
-                h.copy_(self.trend[off:off + size], non_blocking=True)
-                outs.append(h)
+                tok, tbuf, mem = self._pinned(self.ring_out, 4 * size)
+                tbuf[:4 * size].view(torch.float32).copy_(self.trend[off:off + size],
+                                                          non_blocking=True)
+                outs.append((tok, tbuf, mem[:4 * size].view(np.float32)))
             done = torch.cuda.Event()
             done.record(self.copy_stream)
-        return (done, outs)
+        return (done, outs, [u[1] for u in uploads])
 
     def ready(self, handle) -> bool:
         return handle[0].query()
 
     def results(self, handle):
         handle[0].synchronize()
-        return [h.numpy() for h in handle[1]]
+        res = []
+        for tok, _, arr in handle[1]:
+            res.append(arr.copy())  # the ring block is reused right away
+            if tok is not None:
+                self.ring_out.release(tok)
+        for tok in handle[2]:  # the step is done, so its uploads are too
+            if tok is not None:
+                self.ring_in.release(tok)
+        return res
 
     def close(self):
         self.plan.destroy()
@@ -330,7 +442,9 @@ class Server:
             return fut
         req = Request(next(self._ids), flux, time_, int(W), float(alpha), float(c), int(iters),
                       arrival, fut)
+        submitted = self.clock()
         with self._lock:
+            self.stats.submit_lag.append(submitted - arrival)
             if self._closing:
                 raise RuntimeError("server is closed")
             if self.stats.first_arrival is None or arrival < self.stats.first_arrival:
@@ -353,6 +467,12 @@ class Server:
         with self._lock:
             return self.stats.summary(self.arena)
 
+    def reset_stats(self):
+        """Start a new measurement window (e.g. after a warm-up)."""
+        with self._lock:
+            self.stats = Stats()
+            self.arena.high_water = self.arena.used
+
     # -- scheduler ---------------------------------------------------------
     def _admit(self):
         """Admit waiting requests FIFO into contiguous arena groups per key."""
@@ -374,7 +494,8 @@ class Server:
         groups = []
         for req in admitted:
             g = groups[-1] if groups else None
-            if g is not None and g.key == req.key and g.offset + g.size == req.offset:
+            if (g is not None and g.key == req.key and g.offset + g.size == req.offset
+                    and len(g.requests) < self.max_step_curves):
                 g.requests.append(req)
                 g.size += req.n
             else:
@@ -383,9 +504,12 @@ class Server:
 
     def _upload(self, groups):
         for g in groups:
-            flux = np.concatenate([r.flux for r in g.requests]) if len(g.requests) > 1 else g.requests[0].flux
-            tim = np.concatenate([r.time for r in g.requests]) if len(g.requests) > 1 else g.requests[0].time
-            g.upload = self.ex.upload(g.offset, flux, tim)
+            parts = [(r.flux, r.time) for r in g.requests]
+            if hasattr(self.ex, "stage_upload"):
+                g.upload = self.ex.stage_upload(g.offset, parts)
+            else:
+                g.upload = self.ex.upload(g.offset, np.concatenate([p[0] for p in parts]),
+                                          np.concatenate([p[1] for p in parts]))
 
     def _next_step(self):
         """The oldest admitted key's groups, up to the step's curve limit."""
@@ -393,13 +517,10 @@ class Server:
             return None
         key = self._groups[0].key
         chosen, n = [], 0
-        for g in self._groups:
+        for g in self._groups:  # groups never exceed max_step_curves (see _admit)
             if g.key == key and n + len(g.requests) <= self.max_step_curves:
                 chosen.append(g)
                 n += len(g.requests)
-            elif g.key == key and not chosen:
-                chosen.append(g)  # a group is never split
-                break
         for g in chosen:
             self._groups.remove(g)
         return Step(chosen)
@@ -416,6 +537,7 @@ class Server:
                                          [(g.offset, g.size) for g in step.groups])
             step.launched_at = now
             self.stats.steps += 1
+            self.stats.step_curves.append(len(reqs))
             return True
         except Exception as e:  # a failed step fails only its own requests
             self._finish(step, error=e)
@@ -429,40 +551,60 @@ class Server:
             except Exception as e:
                 error = e
         now = self.clock()
+        settle = []
         for gi, g in enumerate(step.groups):
             pos = 0
             for r in g.requests:
                 r.done = now
                 if error is None:
-                    res = outs[gi][pos:pos + r.n]
-                    if not r.future.cancelled():
-                        r.future.set_result(res)
+                    settle.append((r, outs[gi][pos:pos + r.n]))
                     self.stats.completed += 1
                     self.stats.samples += r.n
                     self.stats.latencies.append(now - r.arrival)
+                    self.stats.queued.append(r.admitted - r.arrival)
+                    self.stats.staged.append(r.launched - r.admitted)
+                    self.stats.service.append(now - r.launched)
                 else:
-                    if not r.future.cancelled():
-                        r.future.set_exception(error)
+                    settle.append((r, None))
                     self.stats.failed += 1
                 pos += r.n
             self.arena.free(g.offset, g.size)
         self.stats.last_done = now
+        for r, res in settle:  # statistics are complete before any caller wakes
+            if r.future.cancelled():
+                continue
+            if error is None:
+                r.future.set_result(res)
+            else:
+                r.future.set_exception(error)
 
     def _loop(self):
+        clk = self.clock
         try:
             while True:
+                t0 = clk()
                 with self._lock:
                     # completions first: they free memory for admissions
                     while self._inflight and self.ex.ready(self._inflight[0].handle):
                         self._finish(self._inflight.popleft())
+                    t1 = clk()
                     groups = self._admit()
+                    t2 = clk()
                 self._upload(groups)
+                t3 = clk()
                 with self._lock:
                     self._groups.extend(groups)
                     while self._groups and len(self._inflight) < self.max_inflight:
                         step = self._next_step()
                         if self._launch(step):
                             self._inflight.append(step)
+                    t4 = clk()
+                    ph = self.stats.phase_s
+                    ph["finish"] += t1 - t0
+                    ph["admit"] += t2 - t1
+                    ph["upload"] += t3 - t2
+                    ph["launch"] += t4 - t3
+                    self.stats.loop_max_s = max(self.stats.loop_max_s, t4 - t0)
                     idle = not self._inflight and not self._groups
                     if idle and not self._waiting and self._closing:
                         return
@@ -480,3 +622,48 @@ class Server:
                     if not r.future.done():
                         r.future.set_exception(RuntimeError("scheduler failed: %r" % e))
                 self._waiting.clear()
+
+
+# ---------------------------------------------------------------------------
+# open-loop driver
+
+
+def run_open_loop(server: Server, curves, arrivals, keep_results=None, pause_gc=True):
+    """Submit ``curves[i % len(curves)]`` at times ``arrivals`` (seconds from
+    the start) regardless of completions, then wait for all of them.
+    ``keep_results(i)`` selects the requests whose results are returned.
+    With ``pause_gc`` the cyclic garbage collector is frozen and paused for
+    the measured window (its full sweeps over ~1e5 live requests otherwise
+    stall both the scheduler and the arrival generator for tens of ms).
+    Returns (summary, {i: (curve index, result)})."""
+    import gc
+    if pause_gc:
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+    try:
+        return _open_loop(server, curves, arrivals, keep_results)
+    finally:
+        if pause_gc:
+            gc.enable()
+            gc.unfreeze()
+
+
+def _open_loop(server, curves, arrivals, keep_results):
+    t0 = server.clock()
+    futs = []
+    for i, at in enumerate(arrivals):
+        target = t0 + float(at)
+        while True:
+            now = server.clock()
+            if now >= target:
+                break
+            _time.sleep(min(target - now, 0.001))
+        f, t, W = curves[i % len(curves)]
+        futs.append(server.submit(f, t, W, arrival=target))
+    kept = {}
+    for i, fu in enumerate(futs):
+        res = fu.result()
+        if keep_results is not None and keep_results(i):
+            kept[i] = (i % len(curves), res)
+    return server.summary(), kept

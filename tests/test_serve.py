@@ -185,3 +185,59 @@ def test_latency_is_measured_from_scheduled_arrival():
     s = srv.summary()
     srv.close()
     assert s["p50_ms"] >= 500
+
+
+def test_admission_groups_respect_the_step_limit():
+    class Checking(FakeExecutor):
+        def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+            assert len(offsets) <= 7
+            return super().launch(offsets, lengths, Ws, key, uploads, ranges)
+    gate = threading.Event()
+    srv = Server(Checking(100000, delay=0.001), max_step_curves=7)
+    futs = [srv.submit(np.ones(20, np.float32), W=5) for _ in range(50)]
+    for fu in futs:
+        fu.result(timeout=10)
+    s = srv.summary()
+    srv.close()
+    assert s["completed"] == 50 and s["steps"] >= 8
+
+
+class _FakeTorch:
+    """Enough of torch for PinnedRing on the CPU (no pinned memory here)."""
+    uint8 = np.uint8
+
+    class _T:
+        def __init__(self, n):
+            self.a = np.zeros(n, np.uint8)
+
+        def numpy(self):
+            return self.a
+
+    @classmethod
+    def empty(cls, n, dtype=None, pin_memory=False):
+        return cls._T(n)
+
+
+@settings(max_examples=80, deadline=None)
+@given(st.lists(st.tuples(st.booleans(), st.integers(1, 3000)), max_size=80))
+def test_pinned_ring_blocks_never_overlap(ops):
+    from paper_2604_06602_amd.serve import PinnedRing
+    ring = PinnedRing(_FakeTorch, 8192)
+    live = []
+    for is_alloc, n in ops:
+        if is_alloc or not live:
+            got = ring.alloc(n)
+            if got is None:
+                continue
+            tok, start = got
+            assert 0 <= start and start + n <= ring.size
+            for t2, s2, n2 in live:
+                assert start + n <= s2 or s2 + n2 <= start, "overlapping live blocks"
+            live.append((tok, start, n))
+        else:
+            tok, _, _ = live.pop(len(live) // 3)
+            ring.release(tok)
+    for tok, _, _ in live:
+        ring.release(tok)
+    assert not ring.live
+    assert ring.alloc(8192) is not None  # everything came back
