@@ -27,8 +27,11 @@ BUCKETS = [(31, 25), (127, 121), (383, 361), (767, 721), (2047, 1441)]  # (W_max
 GROUPS = [1, 2, 3, 4]
 
 
+MAX_TILE = 3 * THREADS    # at most three output positions per lane
+
+
 def max_tile(W: int) -> int:
-    return max(1, STAGE_MAX - (W - 1))
+    return max(1, min(MAX_TILE, STAGE_MAX - (W - 1)))
 
 
 TIE = 0.015

@@ -65,8 +65,9 @@ struct TuneRow {
 std::mutex g_tune_mu;
 std::vector<TuneRow> g_tune;  // empty = built-in defaults
 
-// Largest tile whose staged span (tile + W - 1) fits kStageMax.
-int max_tile(int W) { return std::max(1, kStageMax - (W - 1)); }
+// Largest tile: its staged span (tile + W - 1) fits kStageMax, and each lane
+// takes at most three of its positions.
+int max_tile(int W) { return std::max(1, std::min(kMaxTile, kStageMax - (W - 1))); }
 
 // Built-in default: the largest tile, cut back to a whole number of
 // workgroup-wide passes when its last pass would leave most lanes idle.
@@ -735,7 +736,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.2.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.3.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

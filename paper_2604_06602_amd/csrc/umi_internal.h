@@ -12,6 +12,7 @@ constexpr int kStageMax = 2048;
 constexpr int kStageLog2 = 11;
 constexpr int kWords = kStageMax / 64 + 1;  // bit-vector words incl. sentinel
 constexpr int kMainThreads = 512;            // threads per main-kernel workgroup
+constexpr int kMaxTile = 3 * kMainThreads;   // output positions per tile: <= 3 per lane
 constexpr int kPrepThreads = 256;            // threads per pre-pass workgroup
 constexpr int kPrepItems = 4;                // samples per pre-pass thread per chunk
 constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1

@@ -32,6 +32,11 @@
 
 #include "umi_internal.h"
 
+// Every fused multiply-add below is written out with __builtin_fmaf; the
+// compiler may not contract anything else, so the same window gives the same
+// bits whichever code path (fused multi-window or single-window) computes it.
+#pragma clang fp contract(off)
+
 namespace umi {
 
 // ---------------------------------------------------------------------------
@@ -361,9 +366,8 @@ __device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int 
         // Eq. 3: (1 - ue^2)^2 on |ue| < 1, else 0.  1 - ue^2 <= 1 always, so
         // clamping to [0, 1] is exactly max(., 0).
         const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
-        const float wgt = t * t;
-        sw += wgt;
-        swu = __builtin_fmaf(wgt, u, swu);
+        sw = __builtin_fmaf(t, t, sw);
+        swu = __builtin_fmaf(t * t, u, swu);
     }
     sw_out = sw;
     swu_out = swu;
@@ -396,6 +400,212 @@ __device__ __forceinline__ float upper_ssq(const float* __restrict__ xv, int c0,
     return ssq;
 }
 
+// Accumulate one sample into a window's Phase 3 sums (same arithmetic as
+// bisquare_sums).
+template <bool kMin>
+__device__ __forceinline__ void bisquare_acc(float x, float k, float b, float alpha, float& sw,
+                                             float& swu)
+{
+    const float u = __builtin_fmaf(x, k, b);
+    const float au = alpha * u;
+    const float ue = kMin ? __builtin_fminf(u, au) : __builtin_fmaxf(u, au);
+    const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
+    sw = __builtin_fmaf(t, t, sw);
+    swu = __builtin_fmaf(t * t, u, swu);
+}
+
+// R windows that start at consecutive compacted samples x[0], x[1], ...,
+// x[R-1], each n samples long (n >= R): one LDS read feeds every window that
+// contains the sample, and each window still sums its samples in index
+// order, so the result equals R single-window sweeps bit for bit.
+template <int R, bool kMin>
+__device__ __forceinline__ void bisquare_multi(const float* __restrict__ x, int n, const float* k,
+                                               float* mu, bool* act, float alpha, int iters)
+{
+    for (int it = 0; it < iters; ++it) {
+        float b[R], sw[R], swu[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            b[r] = -mu[r] * k[r];
+            sw[r] = 0.0f;
+            swu[r] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < R - 1; ++j) {  // head: windows 0..j
+            const float xj = x[j];
+#pragma unroll
+            for (int r = 0; r <= j; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+        }
+#pragma unroll 4
+        for (int j = R - 1; j < n; ++j) {  // every window
+            const float xj = x[j];
+#pragma unroll
+            for (int r = 0; r < R; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+        }
+#pragma unroll
+        for (int d = 1; d < R; ++d) {  // tail: windows d..R-1 take sample n-1+d
+            const float xj = x[n - 1 + d];
+#pragma unroll
+            for (int r = d; r < R; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (act[r]) {
+                if (sw[r] > 0.0f)
+                    mu[r] = mu[r] + swu[r] / (sw[r] * k[r]);  // Eq. 4 in residual form
+                else
+                    act[r] = false;  // no weight left: keep mu from now on
+            }
+        }
+    }
+}
+
+// Phase 2 sums for R consecutive windows (see bisquare_multi).
+template <int R>
+__device__ __forceinline__ void upper_ssq_multi(const float* __restrict__ x, int n, const float* m,
+                                                float* ssq)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) ssq[r] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < R - 1; ++j) {
+        const float xj = x[j];
+#pragma unroll
+        for (int r = 0; r <= j; ++r) {
+            const float d = __builtin_fmaxf(xj - m[r], 0.0f);
+            ssq[r] = __builtin_fmaf(d, d, ssq[r]);
+        }
+    }
+#pragma unroll 4
+    for (int j = R - 1; j < n; ++j) {
+        const float xj = x[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float d = __builtin_fmaxf(xj - m[r], 0.0f);
+            ssq[r] = __builtin_fmaf(d, d, ssq[r]);
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < R; ++d) {
+        const float xj = x[n - 1 + d];
+#pragma unroll
+        for (int r = d; r < R; ++r) {
+            const float dd = __builtin_fmaxf(xj - m[r], 0.0f);
+            ssq[r] = __builtin_fmaf(dd, dd, ssq[r]);
+        }
+    }
+}
+
+// The windows of one tile: each lane takes R consecutive output positions.
+template <int R>
+__device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int nv,
+                                             const CurveDesc& cd, int h, int s0, int t0, int t1,
+                                             const int32_t* __restrict__ segid,
+                                             const int4* __restrict__ segtab, float alpha,
+                                             float c, int iters, float* __restrict__ trend,
+                                             float* __restrict__ median)
+{
+    const int m_min = max(1, cd.W / 3);
+    const int pfirst = t0 + (int)threadIdx.x * R;
+    uint32_t ca[R], n[R];
+    bool live[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = pfirst + r;
+        live[r] = false;
+        ca[r] = 0;
+        n[r] = 0;
+        if (p < t1) {
+            const int sidp = segid[cd.off + p];
+            if (sidp >= 0) {
+                const int4 seg = segtab[cd.off + sidp];
+                if (seg.w - seg.z >= m_min) {
+                    const int a = max(p - h, seg.x) - s0;
+                    const int b = min(p + h, seg.y) - s0 + 1;
+                    ca[r] = rank1(sm.vbits, sm.vpre, (uint32_t)a);
+                    n[r] = rank1(sm.vbits, sm.vpre, (uint32_t)b) - ca[r];  // >= 1: p is valid
+                    live[r] = true;
+                }
+            }
+        }
+    }
+    // The common case -- every window of the wave live, of one length, and
+    // consecutive -- runs the fused loops with a wave-uniform trip count.
+    const uint32_t n_u = __builtin_amdgcn_readfirstlane(n[0]);
+    bool mine = live[0] && n[0] == n_u && n_u >= (uint32_t)R;
+#pragma unroll
+    for (int r = 1; r < R; ++r) mine = mine && live[r] && n[r] == n_u && ca[r] == ca[0] + r;
+    const bool uniform = __all(mine);
+
+    // Phase 1 (median) and the count of points above it, per window
+    float m[R];
+    uint32_t nplus[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        m[r] = 0.0f;
+        nplus[r] = 0;
+        if (live[r]) {
+            const uint32_t cb = ca[r] + n[r];
+            const uint32_t rk = wavelet_kth(sm, levels, ca[r], cb, (n[r] - 1) >> 1);
+            m[r] = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
+            // the points strictly above m are the window's elements ranked
+            // after the last tile element numerically equal to m (ties and
+            // -0/+0 sit next to m in the sorted order)
+            uint32_t rh = rk;
+            while (rh + 1 < (uint32_t)nv && key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m[r])
+                ++rh;
+            nplus[r] = n[r] - wavelet_count_less(sm, levels, ca[r], cb, rh + 1);
+        }
+    }
+    // Phase 2 (Eq. 1)
+    float ssq[R];
+    if (uniform) {
+        upper_ssq_multi<R>(sm.xv + ca[0], (int)n_u, m, ssq);
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ssq[r] = live[r] ? upper_ssq(sm.xv, (int)ca[r], (int)n[r], m[r]) : 0.0f;
+    }
+    float k[R], mu[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        mu[r] = m[r];
+        k[r] = 0.0f;
+        act[r] = false;
+        if (live[r] && nplus[r] > 0 && iters > 0) {
+            const float s = kScaleConst * __builtin_sqrtf(ssq[r] / (float)nplus[r]);
+            const float kk = 1.0f / (c * s);
+            if (s > 0.0f && isfinite(kk)) {
+                k[r] = kk;
+                act[r] = true;
+            }
+        }
+    }
+    // Phase 3 (Eqs. 2-4)
+    if (alpha >= 1.0f) {
+        if (uniform) {
+            bisquare_multi<R, true>(sm.xv + ca[0], (int)n_u, k, mu, act, alpha, iters);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (act[r]) mu[r] = bisquare<true>(sm.xv, (int)ca[r], (int)n[r], m[r], k[r], alpha, iters);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (act[r]) mu[r] = bisquare<false>(sm.xv, (int)ca[r], (int)n[r], m[r], k[r], alpha, iters);
+    }
+    const float nanf_ = __builtin_nanf("");
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int p = pfirst + r;
+        if (p < t1) {
+            trend[cd.off + p] = live[r] ? mu[r] : nanf_;
+            if (median) median[cd.off + p] = live[r] ? m[r] : nanf_;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const float* __restrict__ flux, const int32_t* __restrict__ segid,
     const int4* __restrict__ segtab, const BatchHeader* __restrict__ hdr,
@@ -407,7 +617,6 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wave = tid >> 6;
-    const float nanf_ = __builtin_nanf("");
     const float alpha = hdr->alpha;
     const float c = hdr->c;
     const int iters = hdr->iters;
@@ -518,73 +727,14 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             __syncthreads();
         }
 
-        // --- one window per lane at a time ---
-        const int m_min = max(1, cd.W / 3);
-        for (int base = t0; base < t1; base += kMainThreads) {
-            const int p = base + tid;
-            const int64_t gp = cd.off + p;
-            bool live = false;
-            uint32_t ca = 0, n = 0;
-            if (p < t1) {
-                const int sidp = segid[gp];
-                if (sidp >= 0) {
-                    const int4 seg = segtab[cd.off + sidp];
-                    if (seg.w - seg.z >= m_min) {
-                        const int a = max(p - h, seg.x) - s0;
-                        const int b = min(p + h, seg.y) - s0 + 1;
-                        ca = rank1(sm.vbits, sm.vpre, (uint32_t)a);
-                        n = rank1(sm.vbits, sm.vpre, (uint32_t)b) - ca;  // >= 1: p is valid
-                        live = true;
-                    }
-                }
-            }
-            // Windows of equal length across the whole wave (the common case)
-            // run their sample loops with a wave-uniform trip count.
-            const uint32_t n_u = __builtin_amdgcn_readfirstlane(n);
-            const bool uniform = __all(live && n == n_u);
-            float out_t = nanf_, out_m = nanf_;
-            if (live) {
-                const uint32_t cb = ca + n;
-                const uint32_t r = wavelet_kth(sm, levels, ca, cb, (n - 1) >> 1);
-                const float m = key_value((uint32_t)(sm.sortbuf[r] >> 32));
-                // Phase 2, Eq. 1: upper-RMS about the median.  The points
-                // strictly above m are the window's elements ranked after the
-                // last tile element numerically equal to m (ties and -0/+0 sit
-                // next to m in the sorted order), counted with one wavelet
-                // descent instead of a compare per sample.
-                uint32_t rh = r;
-                while (rh + 1 < (uint32_t)nv &&
-                       key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m)
-                    ++rh;
-                const uint32_t nplus = n - wavelet_count_less(sm, levels, ca, cb, rh + 1);
-                float ssq;
-                if (uniform)  // wave-uniform branch: separate loop bodies
-                    ssq = upper_ssq(sm.xv, (int)ca, (int)n_u, m);
-                else
-                    ssq = upper_ssq(sm.xv, (int)ca, (int)n, m);
-                float mu = m;
-                if (nplus > 0 && iters > 0) {
-                    const float s = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
-                    const float k = 1.0f / (c * s);
-                    if (s > 0.0f && isfinite(k)) {
-                        if (alpha >= 1.0f) {
-                            if (uniform)
-                                mu = bisquare<true>(sm.xv, (int)ca, (int)n_u, m, k, alpha, iters);
-                            else
-                                mu = bisquare<true>(sm.xv, (int)ca, (int)n, m, k, alpha, iters);
-                        } else {
-                            mu = bisquare<false>(sm.xv, (int)ca, (int)n, m, k, alpha, iters);
-                        }
-                    }
-                }
-                out_t = mu;
-                out_m = m;
-            }
-            if (p < t1) {
-                trend[gp] = out_t;
-                if (median) median[gp] = out_m;
-            }
-        }
+        // --- the tile's windows: R consecutive positions per lane ---
+        const int R = (t1 - t0 + kMainThreads - 1) / kMainThreads;  // tile <= kMaxTile -> R <= 3
+        if (R == 3)
+            tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
+        else if (R == 2)
+            tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
+        else
+            tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
         __syncthreads();
     }
 }

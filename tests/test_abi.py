@@ -165,15 +165,15 @@ def test_autotune_table_is_loadable(lib, monkeypatch):
     rows = [tuple(map(int, l.split())) for l in table.strip().splitlines()]
     assert [r[0] for r in rows] == [b[0] for b in autotune.BUCKETS]
     for w_max, tile, gpc in rows:
-        assert 1 <= tile <= autotune.max_tile(w_max) or tile <= autotune.max_tile(
-            dict(autotune.BUCKETS)[w_max])
+        assert 1 <= tile <= autotune.max_tile(dict(autotune.BUCKETS)[w_max])
         assert 1 <= gpc <= 4
 
 
 def test_autotune_candidates():
     from paper_2604_06602_amd import autotune
-    assert autotune.default_tile(361) == 1536 and autotune.default_tile(25) == 2024
+    assert autotune.default_tile(361) == 1536 and autotune.default_tile(25) == 1536
     assert autotune.default_tile(721) == 1328 and autotune.default_tile(2047) == 2
+    assert autotune.max_tile(25) == 1536 and autotune.max_tile(1441) == 608
     for W in [25, 121, 361, 721, 1441]:
         c = autotune.tile_candidates(W)
         assert autotune.default_tile(W) in c and max(c) == autotune.max_tile(W)

@@ -39,9 +39,10 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
     ex = GpuExecutor(capacity=total // 2, max_curves=64, max_W=721)  # budget forces queueing
     srv = Server(ex)
     futs = []
-    for f, t, W in curves:
+    for i, (f, t, W) in enumerate(curves):
         futs.append(srv.submit(f, t, W))
-        time.sleep(float(rng.exponential(0.002)))  # arrivals while steps run
+        if i % 10 == 9:  # bursts of ten: later arrivals find earlier ones on the GPU
+            time.sleep(float(rng.exponential(0.002)))
     results = [fu.result(timeout=120) for fu in futs]
     summary = srv.summary()
     srv.close()
