@@ -10,7 +10,10 @@ from .oracle import (  # noqa: F401
     detrend,
     detrend_at,
     detrend_batch,
+    mad_scale,
     median,
+    normalise,
+    SCALES,
     segments,
     upper_scale,
     weight,

@@ -75,12 +75,42 @@ def _load():
         lib.umi_oracle_detrend_at.argtypes = [_f32p, _f64p, ctypes.c_int64, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               _i64p, ctypes.c_int64, _f64p, _f32p]
+        lib.umi_oracle_mad_scale.restype = ctypes.c_double
+        lib.umi_oracle_mad_scale.argtypes = [_f32p, ctypes.c_int, ctypes.c_double]
+        lib.umi_oracle_window_ex.restype = ctypes.c_double
+        lib.umi_oracle_window_ex.argtypes = [_f32p, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                             _f32p, _f64p]
+        lib.umi_oracle_detrend_ex.restype = ctypes.c_int
+        lib.umi_oracle_detrend_ex.argtypes = [_f32p, _f64p, ctypes.c_int64, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, _f64p, _f32p]
+        lib.umi_oracle_detrend_at_ex.restype = ctypes.c_int
+        lib.umi_oracle_detrend_at_ex.argtypes = [_f32p, _f64p, ctypes.c_int64, ctypes.c_int,
+                                                 ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                 ctypes.c_int, _i64p, ctypes.c_int64, _f64p,
+                                                 _f32p]
+        lib.umi_oracle_detrend_batch_ex.restype = ctypes.c_int
+        lib.umi_oracle_detrend_batch_ex.argtypes = [_f32p, _f64p, _i64p, ctypes.c_int64, _i32p,
+                                                    _f64p, _f64p, ctypes.c_int, ctypes.c_int,
+                                                    _f64p, _f32p, ctypes.c_int]
+        lib.umi_oracle_normalise.restype = None
+        lib.umi_oracle_normalise.argtypes = [_f32p, _f64p, ctypes.c_int64, _f64p]
         lib.umi_oracle_detrend_batch.restype = ctypes.c_int
         lib.umi_oracle_detrend_batch.argtypes = [_f32p, _f64p, _i64p, ctypes.c_int64, _i32p,
                                                  ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                  _f64p, _f32p, ctypes.c_int]
         _lib = lib
         return lib
+
+
+SCALES = {"upper_rms": 0, "mad": 1}  # Section 2.2 / the MAD ablation
+
+
+def _scale(scale) -> int:
+    if scale not in SCALES:
+        raise ValueError("scale must be one of %s" % sorted(SCALES))
+    return SCALES[scale]
 
 
 def _ptr(a, typ):
@@ -117,13 +147,20 @@ def upper_scale(x, m: float) -> float:
     return float(_load().umi_oracle_upper_scale(_ptr(x, _f32p), int(x.size), float(m)))
 
 
-def window(x, alpha=2.0, c=5.0, iters=5):
+def mad_scale(x, m: float) -> float:
+    """The MAD ablation's scale: lower median of |x - m| (no 0.6745 factor)."""
+    x = _f32(x)
+    return float(_load().umi_oracle_mad_scale(_ptr(x, _f32p), int(x.size), float(m)))
+
+
+def window(x, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
     """One window's estimate: returns (trend, median, scale)."""
     x = _f32(x)
     med = ctypes.c_float()
     sc = ctypes.c_double()
-    t = _load().umi_oracle_window(_ptr(x, _f32p), int(x.size), float(alpha), float(c),
-                                  int(iters), ctypes.byref(med), ctypes.byref(sc))
+    t = _load().umi_oracle_window_ex(_ptr(x, _f32p), int(x.size), float(alpha), float(c),
+                                     int(iters), _scale(scale), ctypes.byref(med),
+                                     ctypes.byref(sc))
     return float(t), np.float32(med.value), float(sc.value)
 
 
@@ -139,7 +176,7 @@ def segments(flux, time, W):
     return lo, hi
 
 
-def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5):
+def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
     """Whole curve: returns (trend float64, median float32)."""
     flux = _f32(flux)
     time = _f64(time)
@@ -148,32 +185,34 @@ def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5):
     n = flux.size
     trend = np.empty(n, np.float64)
     med = np.empty(n, np.float32)
-    rc = _load().umi_oracle_detrend(_ptr(flux, _f32p), _ptr(time, _f64p), n, int(W),
-                                    float(alpha), float(c), int(iters),
-                                    _ptr(trend, _f64p), _ptr(med, _f32p))
+    rc = _load().umi_oracle_detrend_ex(_ptr(flux, _f32p), _ptr(time, _f64p), n, int(W),
+                                       float(alpha), float(c), int(iters), _scale(scale),
+                                       _ptr(trend, _f64p), _ptr(med, _f32p))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med
 
 
-def detrend_at(flux, time, W, idx, alpha=2.0, c=5.0, iters=5):
+def detrend_at(flux, time, W, idx, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
     """Estimates only at positions ``idx`` of one curve."""
     flux = _f32(flux)
     time = _f64(time)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     trend = np.empty(idx.size, np.float64)
     med = np.empty(idx.size, np.float32)
-    rc = _load().umi_oracle_detrend_at(_ptr(flux, _f32p), _ptr(time, _f64p), flux.size,
-                                       int(W), float(alpha), float(c), int(iters),
-                                       _ptr(idx, _i64p), idx.size, _ptr(trend, _f64p),
-                                       _ptr(med, _f32p))
+    rc = _load().umi_oracle_detrend_at_ex(_ptr(flux, _f32p), _ptr(time, _f64p), flux.size,
+                                          int(W), float(alpha), float(c), int(iters),
+                                          _scale(scale), _ptr(idx, _i64p), idx.size,
+                                          _ptr(trend, _f64p), _ptr(med, _f32p))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med
 
 
-def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, n_threads=None):
-    """Packed ragged batch; curves spread over ``n_threads`` host threads."""
+def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, n_threads=None,
+                  scale="upper_rms"):
+    """Packed ragged batch; curves spread over ``n_threads`` host threads.
+    ``W``, ``alpha`` and ``c`` are scalars or one value per curve."""
     flux = _f32(flux)
     time = _f64(time)
     lengths = np.ascontiguousarray(lengths, dtype=np.int64)
@@ -184,10 +223,25 @@ def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, n_threads=N
         n_threads = os.cpu_count() or 1
     trend = np.empty(flux.size, np.float64)
     med = np.empty(flux.size, np.float32)
-    rc = _load().umi_oracle_detrend_batch(_ptr(flux, _f32p), _ptr(time, _f64p),
-                                          _ptr(lengths, _i64p), lengths.size,
-                                          _ptr(Wa, _i32p), float(alpha), float(c), int(iters),
-                                          _ptr(trend, _f64p), _ptr(med, _f32p), int(n_threads))
+    al = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, np.float64), lengths.shape))
+    ca = np.ascontiguousarray(np.broadcast_to(np.asarray(c, np.float64), lengths.shape))
+    rc = _load().umi_oracle_detrend_batch_ex(_ptr(flux, _f32p), _ptr(time, _f64p),
+                                             _ptr(lengths, _i64p), lengths.size,
+                                             _ptr(Wa, _i32p), _ptr(al, _f64p), _ptr(ca, _f64p),
+                                             int(iters), _scale(scale), _ptr(trend, _f64p),
+                                             _ptr(med, _f32p), int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med
+
+
+def normalise(flux, trend):
+    """Detrended flux: flux / trend, NaN where the trend is NaN."""
+    flux = _f32(flux)
+    trend = np.ascontiguousarray(trend, dtype=np.float64)
+    if trend.size != flux.size:
+        raise ValueError("flux and trend differ in length")
+    out = np.empty(flux.size, np.float64)
+    _load().umi_oracle_normalise(_ptr(flux, _f32p), _ptr(trend, _f64p), flux.size,
+                                 _ptr(out, _f64p))
+    return out

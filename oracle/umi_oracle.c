@@ -38,6 +38,15 @@
  *   R8 if sum(w) == 0 in an iteration the location is left unchanged and the
  *      iterations stop; iters = 0 returns the median;
  *   R9 the constant is exactly 0.6745 as printed.
+ *   R15 (scale ablation) the standard MAD, which Sections 1 and 2.2 contrast
+ *      with the upper-RMS scale and Section 3.1 compares against it, is the
+ *      lower median (rank floor((n-1)/2)) of
+ *      |x - m| over the window, used unscaled: at the Gaussian model it
+ *      equals 0.6745 sigma, the value the upper-RMS scale is normalised to;
+ *   R16 per-curve alpha and c (the use-case settings of Table 4) change
+ *      nothing else: each curve is estimated with its own pair;
+ *   R17 the normalisation stage (a pipeline stage of Table 3) divides the flux
+ *      by the trend: detrended = flux / trend, NaN wherever the trend is NaN.
  *
  * Precision: inputs are float32 (flux) and float64 (time); every arithmetic
  * step is float64; the median is returned as the exact float32 element.
@@ -51,6 +60,8 @@
 
 #define ORACLE_SCALE_CONST 0.6745 /* Section 2.2, after Eq. 1 */
 #define ORACLE_GAP_DAYS 0.5       /* reading R3 */
+#define ORACLE_SCALE_UPPER_RMS 0  /* Section 2.2, Eq. 1 (the method) */
+#define ORACLE_SCALE_MAD 1        /* the ablation, reading R15 */
 
 /* ------------------------------------------------------------------------ */
 /* Window-size rule (Section 2, opening text): W = round(0.5 / dt) | 1.      */
@@ -141,15 +152,37 @@ double umi_oracle_upper_scale(const float* x, int n, double m)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Scale ablation (reading R15): s = lower median of |x_i - m|.              */
+
+static int cmp_f64(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+double umi_oracle_mad_scale(const float* x, int n, double m)
+{
+    if (n <= 0) return NAN;
+    double* dev = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!dev) return NAN;
+    for (int i = 0; i < n; ++i) dev[i] = fabs((double)x[i] - m);
+    qsort(dev, (size_t)n, sizeof(double), cmp_f64);
+    double s = dev[(n - 1) / 2];
+    free(dev);
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One window: Phases 1-3.  Returns the location estimate (the trend value). */
 
 static double window_estimate(const float* x, int n, double alpha, double c,
-                              int iters, uint32_t* keys, float* median_out,
-                              double* scale_out)
+                              int iters, int scale_mode, uint32_t* keys,
+                              float* median_out, double* scale_out)
 {
     float med = median_sorted(x, n, keys);
     double m = (double)med;
-    double s = umi_oracle_upper_scale(x, n, m);
+    double s = (scale_mode == ORACLE_SCALE_MAD) ? umi_oracle_mad_scale(x, n, m)
+                                                : umi_oracle_upper_scale(x, n, m);
     if (median_out) *median_out = med;
     if (scale_out) *scale_out = s;
     double mu = m;
@@ -170,8 +203,9 @@ static double window_estimate(const float* x, int n, double alpha, double c,
     return mu;
 }
 
-double umi_oracle_window(const float* x, int n, double alpha, double c,
-                         int iters, float* median_out, double* scale_out)
+double umi_oracle_window_ex(const float* x, int n, double alpha, double c,
+                            int iters, int scale_mode, float* median_out,
+                            double* scale_out)
 {
     if (n <= 0) {
         if (median_out) *median_out = NAN;
@@ -180,9 +214,17 @@ double umi_oracle_window(const float* x, int n, double alpha, double c,
     }
     uint32_t* keys = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
     if (!keys) return NAN;
-    double r = window_estimate(x, n, alpha, c, iters, keys, median_out, scale_out);
+    double r = window_estimate(x, n, alpha, c, iters, scale_mode, keys, median_out,
+                               scale_out);
     free(keys);
     return r;
+}
+
+double umi_oracle_window(const float* x, int n, double alpha, double c,
+                         int iters, float* median_out, double* scale_out)
+{
+    return umi_oracle_window_ex(x, n, alpha, c, iters, ORACLE_SCALE_UPPER_RMS,
+                                median_out, scale_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -235,8 +277,9 @@ int64_t umi_oracle_segments(const float* flux, const double* time, int64_t n,
 
 static void estimate_at(const float* flux, const double* time, int64_t i, int W,
                         const int64_t* seg_lo, const int64_t* seg_hi,
-                        double alpha, double c, int iters, float* buf,
-                        uint32_t* keys, double* trend_out, float* median_out)
+                        double alpha, double c, int iters, int scale_mode,
+                        float* buf, uint32_t* keys, double* trend_out,
+                        float* median_out)
 {
     if (seg_lo[i] < 0) {
         *trend_out = NAN;
@@ -251,7 +294,7 @@ static void estimate_at(const float* flux, const double* time, int64_t i, int W,
     for (int64_t q = a; q <= b; ++q)
         if (sample_valid(flux, time, q)) buf[n++] = flux[q];
     float med;
-    *trend_out = window_estimate(buf, n, alpha, c, iters, keys, &med, NULL);
+    *trend_out = window_estimate(buf, n, alpha, c, iters, scale_mode, keys, &med, NULL);
     if (median_out) *median_out = med;
 }
 
@@ -266,11 +309,12 @@ static int params_ok(int64_t n, int W, double alpha, double c, int iters)
 
 /* Full curve: trend (FP64) and median (exact float32) at every sample.
  * Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
-int umi_oracle_detrend(const float* flux, const double* time, int64_t n, int W,
-                       double alpha, double c, int iters, double* trend,
-                       float* median)
+int umi_oracle_detrend_ex(const float* flux, const double* time, int64_t n,
+                          int W, double alpha, double c, int iters,
+                          int scale_mode, double* trend, float* median)
 {
     if (!params_ok(n, W, alpha, c, iters)) return -1;
+    if (scale_mode != ORACLE_SCALE_UPPER_RMS && scale_mode != ORACLE_SCALE_MAD) return -1;
     if (n == 0) return 0;
     int64_t* lo = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
     int64_t* hi = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
@@ -283,8 +327,8 @@ int umi_oracle_detrend(const float* flux, const double* time, int64_t n, int W,
     }
     umi_oracle_segments(flux, time, n, W, lo, hi);
     for (int64_t i = 0; i < n; ++i)
-        estimate_at(flux, time, i, W, lo, hi, alpha, c, iters, buf, keys,
-                    &trend[i], median ? &median[i] : NULL);
+        estimate_at(flux, time, i, W, lo, hi, alpha, c, iters, scale_mode, buf,
+                    keys, &trend[i], median ? &median[i] : NULL);
 done:
     free(lo);
     free(hi);
@@ -293,14 +337,23 @@ done:
     return rc;
 }
 
+int umi_oracle_detrend(const float* flux, const double* time, int64_t n, int W,
+                       double alpha, double c, int iters, double* trend,
+                       float* median)
+{
+    return umi_oracle_detrend_ex(flux, time, n, W, alpha, c, iters,
+                                 ORACLE_SCALE_UPPER_RMS, trend, median);
+}
+
 /* Only at the listed positions of one curve (segments still come from the
  * whole curve): used to check sampled outputs of large workloads. */
-int umi_oracle_detrend_at(const float* flux, const double* time, int64_t n,
-                          int W, double alpha, double c, int iters,
-                          const int64_t* idx, int64_t n_idx, double* trend,
-                          float* median)
+int umi_oracle_detrend_at_ex(const float* flux, const double* time, int64_t n,
+                             int W, double alpha, double c, int iters,
+                             int scale_mode, const int64_t* idx, int64_t n_idx,
+                             double* trend, float* median)
 {
     if (!params_ok(n, W, alpha, c, iters) || n_idx < 0) return -1;
+    if (scale_mode != ORACLE_SCALE_UPPER_RMS && scale_mode != ORACLE_SCALE_MAD) return -1;
     for (int64_t k = 0; k < n_idx; ++k)
         if (idx[k] < 0 || idx[k] >= n) return -1;
     if (n_idx == 0) return 0;
@@ -315,14 +368,24 @@ int umi_oracle_detrend_at(const float* flux, const double* time, int64_t n,
     }
     umi_oracle_segments(flux, time, n, W, lo, hi);
     for (int64_t k = 0; k < n_idx; ++k)
-        estimate_at(flux, time, idx[k], W, lo, hi, alpha, c, iters, buf, keys,
-                    &trend[k], median ? &median[k] : NULL);
+        estimate_at(flux, time, idx[k], W, lo, hi, alpha, c, iters, scale_mode,
+                    buf, keys, &trend[k], median ? &median[k] : NULL);
 done:
     free(lo);
     free(hi);
     free(buf);
     free(keys);
     return rc;
+}
+
+int umi_oracle_detrend_at(const float* flux, const double* time, int64_t n,
+                          int W, double alpha, double c, int iters,
+                          const int64_t* idx, int64_t n_idx, double* trend,
+                          float* median)
+{
+    return umi_oracle_detrend_at_ex(flux, time, n, W, alpha, c, iters,
+                                    ORACLE_SCALE_UPPER_RMS, idx, n_idx, trend,
+                                    median);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -337,8 +400,10 @@ typedef struct {
     const int64_t* offsets;
     const int* W;
     int64_t n_curves;
-    double alpha, c;
+    const double* alpha; /* per curve (reading R16) */
+    const double* c;
     int iters;
+    int scale_mode;
     double* trend;
     float* median;
     int64_t next; /* next curve to take, guarded by mu */
@@ -355,10 +420,10 @@ static void* batch_worker(void* arg)
         pthread_mutex_unlock(&job->mu);
         if (b >= job->n_curves) break;
         int64_t off = job->offsets[b];
-        int rc = umi_oracle_detrend(
+        int rc = umi_oracle_detrend_ex(
             job->flux + off, job->time ? job->time + off : NULL, job->lengths[b],
-            job->W[b], job->alpha, job->c, job->iters, job->trend + off,
-            job->median ? job->median + off : NULL);
+            job->W[b], job->alpha[b], job->c[b], job->iters, job->scale_mode,
+            job->trend + off, job->median ? job->median + off : NULL);
         if (rc != 0) {
             pthread_mutex_lock(&job->mu);
             job->rc = rc;
@@ -368,10 +433,12 @@ static void* batch_worker(void* arg)
     return NULL;
 }
 
-int umi_oracle_detrend_batch(const float* flux, const double* time,
-                             const int64_t* lengths, int64_t n_curves,
-                             const int* W, double alpha, double c, int iters,
-                             double* trend, float* median, int n_threads)
+/* Per-curve alpha[b] and c[b] (reading R16) and a scale mode (R15). */
+int umi_oracle_detrend_batch_ex(const float* flux, const double* time,
+                                const int64_t* lengths, int64_t n_curves,
+                                const int* W, const double* alpha,
+                                const double* c, int iters, int scale_mode,
+                                double* trend, float* median, int n_threads)
 {
     if (n_curves < 0) return -1;
     if (n_curves == 0) return 0;
@@ -386,8 +453,8 @@ int umi_oracle_detrend_batch(const float* flux, const double* time,
         offsets[b] = acc;
         acc += lengths[b];
     }
-    batch_job job = {flux, time, lengths, offsets, W, n_curves, alpha, c,
-                     iters, trend, median, 0, PTHREAD_MUTEX_INITIALIZER, 0};
+    batch_job job = {flux, time, lengths, offsets, W, n_curves, alpha, c, iters,
+                     scale_mode, trend, median, 0, PTHREAD_MUTEX_INITIALIZER, 0};
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
     pthread_t tids[256];
@@ -400,4 +467,38 @@ int umi_oracle_detrend_batch(const float* flux, const double* time,
     for (int t = 0; t < started; ++t) pthread_join(tids[t], NULL);
     free(offsets);
     return job.rc;
+}
+
+int umi_oracle_detrend_batch(const float* flux, const double* time,
+                             const int64_t* lengths, int64_t n_curves,
+                             const int* W, double alpha, double c, int iters,
+                             double* trend, float* median, int n_threads)
+{
+    if (n_curves < 0) return -1;
+    if (n_curves == 0) return 0;
+    double* a = (double*)malloc(sizeof(double) * (size_t)n_curves);
+    double* cc = (double*)malloc(sizeof(double) * (size_t)n_curves);
+    int rc = -2;
+    if (a && cc) {
+        for (int64_t b = 0; b < n_curves; ++b) {
+            a[b] = alpha;
+            cc[b] = c;
+        }
+        rc = umi_oracle_detrend_batch_ex(flux, time, lengths, n_curves, W, a, cc,
+                                         iters, ORACLE_SCALE_UPPER_RMS, trend,
+                                         median, n_threads);
+    }
+    free(a);
+    free(cc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normalisation (reading R17): detrended[j] = flux[j] / trend[j].           */
+
+void umi_oracle_normalise(const float* flux, const double* trend, int64_t n,
+                          double* detrended)
+{
+    for (int64_t j = 0; j < n; ++j)
+        detrended[j] = isnan(trend[j]) ? NAN : (double)flux[j] / trend[j];
 }

@@ -76,10 +76,22 @@ def segment_of(flux, time, W):
     return out
 
 
-def estimate(xs, alpha, c, iters):
+def count_mad(xs, m):
+    """MAD ablation scale: the smallest deviation |x - m| that at least
+    floor((n-1)/2) + 1 deviations do not exceed (the lower median of the
+    deviations, found by counting)."""
+    k = (len(xs) - 1) // 2
+    devs = [abs(x - m) for x in xs]
+    return min(d for d in devs if sum(1 for e in devs if e <= d) >= k + 1)
+
+
+def estimate(xs, alpha, c, iters, scale="upper_rms"):
     m = rank_median(xs)
-    up = [x - m for x in xs if x > m]
-    s = SCALE * math.sqrt(sum(d * d for d in up) / len(up)) if up else 0.0
+    if scale == "mad":
+        s = count_mad(xs, m)
+    else:
+        up = [x - m for x in xs if x > m]
+        s = SCALE * math.sqrt(sum(d * d for d in up) / len(up)) if up else 0.0
     mu = m
     if s > 0:
         for _ in range(iters):
@@ -96,7 +108,7 @@ def estimate(xs, alpha, c, iters):
     return mu, m
 
 
-def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5):
+def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
     flux = [f32(float(v)) for v in flux]
     time = None if time is None else [float(v) for v in time]
     n = len(flux)
@@ -110,5 +122,5 @@ def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5):
         lo, hi = seg[i]
         xs = [flux[j] for j in range(n)
               if lo <= j <= hi and i - h <= j <= i + h and valid(flux, time, j)]
-        trend[i], med[i] = estimate(xs, alpha, c, iters)
+        trend[i], med[i] = estimate(xs, alpha, c, iters, scale)
     return trend, med

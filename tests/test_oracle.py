@@ -179,6 +179,101 @@ def test_upper_scale_dip_immunity(oracle_lib):
 
 
 # --------------------------------------------------------------------------
+# The MAD scale ablation (Sections 1, 2.2 and 3.1; reading R15)
+
+
+def test_mad_scale_hand_examples(oracle_lib):
+    # {1..5}, m=3: deviations {2,1,0,1,2} -> sorted {0,1,1,2,2}, rank 2 -> 1
+    assert oracle_lib.mad_scale([1, 2, 3, 4, 5], 3.0) == 1.0
+    # an upward outlier does not move it
+    assert oracle_lib.mad_scale([1, 2, 3, 4, 100], 3.0) == 1.0
+    # {2,7,2,9,1}, m=2: deviations {0,5,0,7,1} -> {0,0,1,5,7} -> 1
+    assert oracle_lib.mad_scale([2, 7, 2, 9, 1], 2.0) == 1.0
+    # even n, lower median of deviations: {0,1}, m=0 -> {0,1} -> 0
+    assert oracle_lib.mad_scale([0, 1], 0.0) == 0.0
+    # window estimate with s = 0 is the median; with s = 1 it is the upper-RMS
+    # iteration run with that scale
+    t, m, s = oracle_lib.window([0.0, 1.0], scale="mad")
+    assert s == 0.0 and t == 0.0 and m == 0.0
+    t, m, s = oracle_lib.window([1, 2, 3, 4, 5], scale="mad")
+    assert m == 3.0 and s == 1.0
+
+
+def test_mad_and_upper_rms_agree_at_the_gaussian_model(oracle_lib):
+    """Section 2.2: the 0.6745 factor makes the upper-RMS scale match the MAD
+    convention at the Gaussian model; both tend to Phi^-1(3/4) sigma."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(31)
+    x = rng.normal(0.0, 1.0, 400001).astype(np.float32)
+    m = float(oracle_lib.median(x))
+    q = norm.ppf(0.75)
+    assert oracle_lib.mad_scale(x, m) == pytest.approx(q, rel=0.01)
+    assert oracle_lib.upper_scale(x, m) == pytest.approx(q, rel=0.01)
+
+
+def test_mad_is_inflated_by_dips_upper_rms_is_not(oracle_lib):
+    """Sections 1 and 2.2: deepening points below the median leaves the
+    upper-RMS scale unchanged but inflates the MAD."""
+    rng = np.random.default_rng(12)
+    for _ in range(10):
+        x = rng.normal(1.0, 1e-3, 361).astype(np.float32)
+        m = float(oracle_lib.median(x))
+        below = np.where(x < m)[0]
+        y = x.copy()
+        y[below[: len(below) // 2]] -= np.float32(0.05)
+        assert float(oracle_lib.median(y)) == m
+        assert oracle_lib.upper_scale(y, m) == oracle_lib.upper_scale(x, m)
+        assert oracle_lib.mad_scale(y, m) > oracle_lib.mad_scale(x, m)
+
+
+# --------------------------------------------------------------------------
+# Per-curve parameters (Table 4) and the normalisation stage (readings R16-R17)
+
+
+def test_table4_presets_per_curve_in_a_batch(oracle_lib):
+    import synth
+    curves = []
+    rng = np.random.default_rng(17)
+    f = (1 + rng.normal(0, 1e-3, 600)).astype(np.float32)
+    f[100:112] -= np.float32(3e-3)
+    for i in range(4):  # one curve, four parameter settings
+        curves.append((f, np.arange(600) * (2 / 1440), 25))
+    packed = synth.lightcurves.pack(curves)
+    presets = [tuple(float(v) for v in PV[k][0].split(",")) for k in
+               ["preset_tess", "preset_kepler", "preset_variable", "preset_max_sensitivity"]]
+    alphas = [a for a, _ in presets]
+    cs = [c for _, c in presets]
+    tr, md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W,
+                                      alpha=alphas, c=cs, n_threads=2)
+    for i, (f, t, W) in enumerate(curves):
+        t1, m1 = oracle_lib.detrend(f, t, W, alpha=alphas[i], c=cs[i])
+        sl = slice(packed.offsets[i], packed.offsets[i] + f.size)
+        assert np.array_equal(t1, tr[sl], equal_nan=True)
+        assert np.array_equal(m1.view(np.uint32), md[sl].view(np.uint32))
+    # inside the dip a larger alpha (and a smaller c) keeps the trend higher
+    # above it: variable (1) < TESS (2) < Kepler (3), and TESS < (10, 2.5)
+    level = [float(tr[packed.offsets[i] + 106]) for i in range(4)]
+    assert level[2] < level[0] < level[1] and level[0] < level[3], level
+
+
+def test_normalise_definition(oracle_lib):
+    f = np.array([2.0, 3.0, np.nan, 5.0], np.float32)
+    tr = np.array([4.0, np.nan, 1.0, 5.0])
+    d = oracle_lib.normalise(f, tr)
+    assert d[0] == 0.5 and np.isnan(d[1]) and np.isnan(d[2]) and d[3] == 1.0
+    # a constant curve normalises to exactly one; power-of-two scaling of the
+    # flux leaves the detrended flux bit-identical
+    rng = np.random.default_rng(9)
+    g = (1 + rng.normal(0, 1e-3, 400)).astype(np.float32)
+    c = np.full(400, 0.75, np.float32)
+    tc, _ = oracle_lib.detrend(c, None, 25)
+    assert (oracle_lib.normalise(c, tc) == 1.0).all()
+    t1, _ = oracle_lib.detrend(g, None, 25)
+    t4, _ = oracle_lib.detrend(g * np.float32(4), None, 25)
+    assert np.array_equal(oracle_lib.normalise(g, t1), oracle_lib.normalise(g * np.float32(4), t4))
+
+
+# --------------------------------------------------------------------------
 # Whole-window estimate, Sections 2.1-2.3
 
 
@@ -337,9 +432,10 @@ def _tiny_cases():
 @pytest.mark.parametrize("case", range(40))
 def test_detrend_matches_bruteforce(oracle_lib, case):
     flux, time, W = _tiny_cases()[case]
-    for a, c, it in [(2.0, 5.0, 5), (1.0, 5.0, 3), (10.0, 2.5, 5)]:
-        tr, md = oracle_lib.detrend(flux, time, W, a, c, it)
-        btr, bmd = bf.detrend(flux, time, W, a, c, it)
+    for a, c, it, sc in [(2.0, 5.0, 5, "upper_rms"), (1.0, 5.0, 3, "upper_rms"),
+                         (10.0, 2.5, 5, "upper_rms"), (2.0, 5.0, 5, "mad")]:
+        tr, md = oracle_lib.detrend(flux, time, W, a, c, it, scale=sc)
+        btr, bmd = bf.detrend(flux, time, W, a, c, it, scale=sc)
         btr = np.array(btr)
         bmd = np.array(bmd, dtype=np.float32)
         assert np.array_equal(np.isnan(tr), np.isnan(btr))
@@ -403,3 +499,5 @@ def test_bad_arguments_rejected(oracle_lib):
                         (5, 2, 5, -1), (5, float("nan"), 5, 5)]:
         with pytest.raises(ValueError):
             oracle_lib.detrend(f, None, W, a, c, it)
+    with pytest.raises(ValueError):
+        oracle_lib.detrend(f, None, 5, scale="iqr")

@@ -34,6 +34,11 @@ MUTANTS = {
     "gap measured from segment start": ("(time[q] - time[last]) > ORACLE_GAP_DAYS", "(time[q] - time[lo]) > ORACLE_GAP_DAYS"),
     "minimum segment W/2 instead of W/3": ("int64_t m_min = W / 3;", "int64_t m_min = W / 2;"),
     "invalid samples kept in windows": ("if (sample_valid(flux, time, q)) buf[n++] = flux[q];", "buf[n++] = flux[q];"),
+    "MAD: upper median of deviations": ("double s = dev[(n - 1) / 2];", "double s = dev[n / 2];"),
+    "MAD: scaled to sigma": ("double s = dev[(n - 1) / 2];", "double s = 1.4826 * dev[(n - 1) / 2];"),
+    "MAD: deviations not absolute": ("dev[i] = fabs((double)x[i] - m);", "dev[i] = (double)x[i] - m;"),
+    "per-curve alpha ignored": ("job->W[b], job->alpha[b], job->c[b],", "job->W[b], job->alpha[0], job->c[b],"),
+    "normalise inverted": ("(double)flux[j] / trend[j];", "trend[j] / (double)flux[j];"),
 }
 
 
