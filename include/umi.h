@@ -83,6 +83,36 @@ typedef struct {
     void* main_stop;       /* optional hipEvent_t recorded just after them */
 } umi_launch;
 
+/* Phase 2 scale estimators. */
+typedef enum {
+    UMI_SCALE_UPPER_RMS = 0, /* the method: s = 0.6745 * sigma_upper from the
+                                points strictly above the median (Section 2.2,
+                                Eq. 1) */
+    UMI_SCALE_MAD = 1        /* ablation: s = the standard MAD, the lower
+                                median (rank floor((n-1)/2)) of |x - m| over
+                                the window, unscaled (it equals 0.6745 sigma
+                                at the Gaussian model); the scale Sections 1
+                                and 2.2 contrast with the upper-RMS one and
+                                Section 3.1 compares against it */
+} umi_scale;
+
+/* Extra options of the _ex calls.  NULL (or all fields zero) is the method
+ * as published with the call's alpha and c for every curve. */
+typedef struct {
+    const float* alpha;  /* [host] n_curves per-curve asymmetry factors, or
+                            NULL for the call's alpha.  The use-case settings
+                            of Table 4 (planet search 2/5, high-precision
+                            3/5, variable stars 1/5, maximum shallow
+                            sensitivity 10/2.5) can be mixed in one batch. */
+    const float* c;      /* [host] n_curves per-curve c, or NULL */
+    int32_t scale;       /* umi_scale */
+    int32_t reserved;    /* must be 0 */
+    float* detrended;    /* device out, or NULL: flux / trend at every sample
+                            of every curve (the normalisation stage Table 3
+                            lists), laid out like trend; NaN where the trend
+                            is NaN.  float32 division, correctly rounded. */
+} umi_options;
+
 /*
  * umi_detrend -- one curve (Section 2; gap handling per Section 4.4).
  *   flux   [n] float32 fluxes.
@@ -137,6 +167,22 @@ umi_status umi_detrend_gather(const float* flux, const double* time,
                               void* stream);
 
 /*
+ * umi_detrend_gather_ex -- umi_detrend_gather with umi_options (per-curve
+ * alpha and c, the scale estimator, a detrended-flux output).  `offsets` may
+ * be NULL: the curves are then packed back to back as for umi_detrend_batch.
+ * Per-curve alpha and c must be finite and > 0 (UMI_ERR_INVALID_ARG
+ * otherwise); `alpha` and `c` arguments of the call are still checked and
+ * used for any field of `options` that is NULL.
+ */
+umi_status umi_detrend_gather_ex(const float* flux, const double* time,
+                                 const int64_t* offsets, const int64_t* lengths,
+                                 int64_t n_curves, const int32_t* W,
+                                 float alpha, float c, int32_t iters,
+                                 float* trend, float* median,
+                                 const umi_options* options,
+                                 const umi_launch* launch, void* stream);
+
+/*
  * Plans: a replayable launch over fixed device arrays, for serving loops.
  * umi_plan_create binds the arrays (each `capacity` samples; time and median
  * may be NULL) and a non-default stream, and allocates the plan's workspace
@@ -163,6 +209,13 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity,
 umi_status umi_plan_run(umi_plan* plan, const int64_t* offsets,
                         const int64_t* lengths, const int32_t* W,
                         int64_t n_curves, float alpha, float c, int32_t iters);
+/* umi_plan_run with umi_options: the per-curve parameters, scale estimator
+ * and detrended output travel with the staged batch, so one captured graph
+ * serves them all.  A detrended array must hold the plan's capacity. */
+umi_status umi_plan_run_ex(umi_plan* plan, const int64_t* offsets,
+                           const int64_t* lengths, const int32_t* W,
+                           int64_t n_curves, float alpha, float c,
+                           int32_t iters, const umi_options* options);
 umi_status umi_plan_destroy(umi_plan* plan);
 
 /* Window-size rule of Section 2: round(window_days / cadence_days) | 1.

@@ -10,6 +10,8 @@ from ._lib import (  # noqa: F401
     MAX_WINDOW,
     MODE_PER_CURVE,
     MODE_PERSISTENT,
+    PRESETS,
+    SCALES,
     LaunchOptions,
     Plan,
     UmiError,

@@ -25,6 +25,10 @@ STATUS_NAMES = {0: "UMI_OK", 1: "UMI_ERR_INVALID_ARG", 2: "UMI_ERR_NO_MEMORY",
 MODE_PERSISTENT = 0
 MODE_PER_CURVE = 1
 MAX_WINDOW = 2047
+SCALES = {"upper_rms": 0, "mad": 1}  # umi_scale
+# Table 4 use-case settings (alpha, c)
+PRESETS = {"tess": (2.0, 5.0), "kepler": (3.0, 5.0), "variable": (1.0, 5.0),
+           "max_sensitivity": (10.0, 2.5)}
 
 
 class UmiError(RuntimeError):
@@ -38,6 +42,11 @@ class Launch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("main_start", ctypes.c_void_p), ("main_stop", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_void_p), ("c", ctypes.c_void_p), ("scale", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("detrended", ctypes.c_void_p)]
 
 
 _vp = ctypes.c_void_p
@@ -66,6 +75,14 @@ def _load():
     lib.umi_detrend_gather.argtypes = [_vp, _vp, _i64p, _i64p, ctypes.c_int64, _i32p,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp, _vp,
                                        ctypes.POINTER(Launch), _vp]
+    lib.umi_detrend_gather_ex.restype = ctypes.c_int
+    lib.umi_detrend_gather_ex.argtypes = [_vp, _vp, _i64p, _i64p, ctypes.c_int64, _i32p,
+                                          ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp,
+                                          _vp, ctypes.POINTER(Options), ctypes.POINTER(Launch),
+                                          _vp]
+    lib.umi_plan_run_ex.restype = ctypes.c_int
+    lib.umi_plan_run_ex.argtypes = [_vp, _i64p, _i64p, _i32p, ctypes.c_int64, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_int32, ctypes.POINTER(Options)]
     lib.umi_plan_create.restype = ctypes.c_int
     lib.umi_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64,
                                     ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
@@ -168,9 +185,41 @@ class LaunchOptions:
                       ev(self.main_start), ev(self.main_stop))
 
 
+def _options(n_curves, alpha, c, scale, detrended_ptr):
+    """(umi_options or None, scalar alpha, scalar c, arrays to keep alive).
+    ``alpha`` and ``c`` are scalars or one value per curve; ``scale`` is a key
+    of SCALES.  None means the plain call suffices."""
+    if scale not in SCALES:
+        raise ValueError("scale must be one of %s" % sorted(SCALES))
+    a_arr = c_arr = None
+    a0 = c0 = None
+    if np.ndim(alpha) == 0:
+        a0 = float(alpha)
+    else:
+        a_arr = np.ascontiguousarray(alpha, dtype=np.float32)
+        if a_arr.shape != (n_curves,):
+            raise ValueError("per-curve alpha needs %d values" % n_curves)
+        a0 = 2.0
+    if np.ndim(c) == 0:
+        c0 = float(c)
+    else:
+        c_arr = np.ascontiguousarray(c, dtype=np.float32)
+        if c_arr.shape != (n_curves,):
+            raise ValueError("per-curve c needs %d values" % n_curves)
+        c0 = 5.0
+    if a_arr is None and c_arr is None and scale == "upper_rms" and detrended_ptr is None:
+        return None, a0, c0, ()
+    o = Options(None if a_arr is None else a_arr.ctypes.data,
+                None if c_arr is None else c_arr.ctypes.data, SCALES[scale], 0, detrended_ptr)
+    return o, a0, c0, (a_arr, c_arr)
+
+
 def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=5.0, iters=5,
-                       launch: LaunchOptions | None = None, stream=None):
-    """Raw batch call on preallocated device tensors (packed ragged layout)."""
+                       launch: LaunchOptions | None = None, stream=None, scale="upper_rms",
+                       detrended=None):
+    """Raw batch call on preallocated device tensors (packed ragged layout).
+    ``alpha``/``c`` may hold one value per curve; ``detrended`` receives
+    flux / trend."""
     torch = _torch()
     lengths = np.ascontiguousarray(lengths, dtype=np.int64)
     Wa = np.ascontiguousarray(np.broadcast_to(np.asarray(W, dtype=np.int32), lengths.shape))
@@ -179,29 +228,47 @@ def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=
     tp = _dev_ptr(time, torch.float64, "time", n)
     op = _dev_ptr(trend, torch.float32, "trend", n)
     mp = _dev_ptr(median, torch.float32, "median", n)
+    dp = _dev_ptr(detrended, torch.float32, "detrended", n)
+    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
     lp = None
     if launch is not None:
         lp = ctypes.byref(launch.as_struct())
-    st = lib.umi_detrend_batch(fp, tp, lengths.ctypes.data_as(_i64p), lengths.size,
-                               Wa.ctypes.data_as(_i32p), float(alpha), float(c), int(iters),
-                               op, mp, lp, _stream_handle(stream))
+    if opts is None:
+        st = lib.umi_detrend_batch(fp, tp, lengths.ctypes.data_as(_i64p), lengths.size,
+                                   Wa.ctypes.data_as(_i32p), a0, c0, int(iters),
+                                   op, mp, lp, _stream_handle(stream))
+    else:
+        st = lib.umi_detrend_gather_ex(fp, tp, None, lengths.ctypes.data_as(_i64p),
+                                       lengths.size, Wa.ctypes.data_as(_i32p), a0, c0,
+                                       int(iters), op, mp, ctypes.byref(opts), lp,
+                                       _stream_handle(stream))
+    del keep
     _check(st)
 
 
 def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, with_median=False,
-                  launch: LaunchOptions | None = None, stream=None):
-    """Packed ragged batch: returns (trend, median or None) as device tensors."""
+                  launch: LaunchOptions | None = None, stream=None, scale="upper_rms",
+                  with_detrended=False):
+    """Packed ragged batch: returns (trend, median or None) as device tensors,
+    plus the detrended flux when ``with_detrended``."""
     torch = _torch()
     trend = torch.empty_like(flux)
     median = torch.empty_like(flux) if with_median else None
-    detrend_batch_into(flux, time, lengths, W, trend, median, alpha, c, iters, launch, stream)
-    return trend, median
+    det = torch.empty_like(flux) if with_detrended else None
+    detrend_batch_into(flux, time, lengths, W, trend, median, alpha, c, iters, launch, stream,
+                       scale, det)
+    return (trend, median, det) if with_detrended else (trend, median)
 
 
-def detrend(flux, time=None, W=361, alpha=2.0, c=5.0, iters=5, with_median=False, stream=None):
-    """One curve: returns (trend, median or None) as device tensors."""
+def detrend(flux, time=None, W=361, alpha=2.0, c=5.0, iters=5, with_median=False, stream=None,
+            scale="upper_rms", with_detrended=False):
+    """One curve: returns (trend, median or None) as device tensors, plus the
+    detrended flux when ``with_detrended``."""
     torch = _torch()
     n = flux.numel()
+    if scale != "upper_rms" or with_detrended:
+        return detrend_batch(flux, time, [n], W, alpha, c, iters, with_median, None, stream,
+                             scale, with_detrended)
     trend = torch.empty_like(flux)
     median = torch.empty_like(flux) if with_median else None
     st = lib.umi_detrend(_dev_ptr(flux, torch.float32, "flux", n),
@@ -235,19 +302,26 @@ def _span_ptr(t, dtype, name, span):
 
 
 def detrend_gather_into(flux, time, offsets, lengths, W, trend, median=None, alpha=2.0, c=5.0,
-                        iters=5, launch: LaunchOptions | None = None, stream=None):
+                        iters=5, launch: LaunchOptions | None = None, stream=None,
+                        scale="upper_rms", detrended=None):
     """Curves at explicit sample offsets of the device arrays (no packing)."""
     torch = _torch()
     offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
     span = int((offsets + np.maximum(lengths, 0)).max()) if lengths.size else 0
     lp = ctypes.byref(launch.as_struct()) if launch is not None else None
-    st = lib.umi_detrend_gather(_span_ptr(flux, torch.float32, "flux", span),
-                                _span_ptr(time, torch.float64, "time", span),
-                                offsets.ctypes.data_as(_i64p), lengths.ctypes.data_as(_i64p),
-                                lengths.size, Wa.ctypes.data_as(_i32p), float(alpha), float(c),
-                                int(iters), _span_ptr(trend, torch.float32, "trend", span),
-                                _span_ptr(median, torch.float32, "median", span), lp,
-                                _stream_handle(stream))
+    dp = _span_ptr(detrended, torch.float32, "detrended", span)
+    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
+    args = (_span_ptr(flux, torch.float32, "flux", span),
+            _span_ptr(time, torch.float64, "time", span),
+            offsets.ctypes.data_as(_i64p), lengths.ctypes.data_as(_i64p),
+            lengths.size, Wa.ctypes.data_as(_i32p), a0, c0,
+            int(iters), _span_ptr(trend, torch.float32, "trend", span),
+            _span_ptr(median, torch.float32, "median", span))
+    if opts is None:
+        st = lib.umi_detrend_gather(*args, lp, _stream_handle(stream))
+    else:
+        st = lib.umi_detrend_gather_ex(*args, ctypes.byref(opts), lp, _stream_handle(stream))
+    del keep
     _check(st)
 
 
@@ -275,13 +349,25 @@ class Plan:
         self.max_curves = int(max_curves)
         self.max_W = int(max_W)
 
-    def run(self, offsets, lengths, W, alpha=2.0, c=5.0, iters=5):
+    def run(self, offsets, lengths, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms",
+            detrended=None):
+        """Stage and replay one batch; ``alpha``/``c`` may hold one value per
+        curve; ``detrended`` (capacity samples) receives flux / trend."""
         if self._h is None:
             raise RuntimeError("plan destroyed")
+        torch = _torch()
         offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
-        st = lib.umi_plan_run(self._h, offsets.ctypes.data_as(_i64p),
-                              lengths.ctypes.data_as(_i64p), Wa.ctypes.data_as(_i32p),
-                              lengths.size, float(alpha), float(c), int(iters))
+        dp = _span_ptr(detrended, torch.float32, "detrended", self.capacity)
+        opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
+        if opts is None:
+            st = lib.umi_plan_run(self._h, offsets.ctypes.data_as(_i64p),
+                                  lengths.ctypes.data_as(_i64p), Wa.ctypes.data_as(_i32p),
+                                  lengths.size, a0, c0, int(iters))
+        else:
+            st = lib.umi_plan_run_ex(self._h, offsets.ctypes.data_as(_i64p),
+                                     lengths.ctypes.data_as(_i64p), Wa.ctypes.data_as(_i32p),
+                                     lengths.size, a0, c0, int(iters), ctypes.byref(opts))
+        del keep
         _check(st)
 
     def destroy(self):

@@ -118,6 +118,25 @@ umi_status check_params(float alpha, float c, int32_t iters)
     return UMI_OK;
 }
 
+// The extra options of the _ex calls (NULL = the plain method with the
+// call's alpha and c for every curve).
+umi_status check_options(const umi_options* o, int64_t n_curves, umi_options* out)
+{
+    *out = umi_options{nullptr, nullptr, UMI_SCALE_UPPER_RMS, 0, nullptr};
+    if (!o) return UMI_OK;
+    *out = *o;
+    if (o->reserved != 0) return fail(UMI_ERR_INVALID_ARG, "umi_options.reserved must be 0");
+    if (o->scale != UMI_SCALE_UPPER_RMS && o->scale != UMI_SCALE_MAD)
+        return fail(UMI_ERR_INVALID_ARG, "unknown umi_options.scale");
+    for (int64_t b = 0; b < n_curves; ++b) {
+        if (o->alpha && !finite_pos(o->alpha[b]))
+            return fail(UMI_ERR_INVALID_ARG, "per-curve alpha must be finite and > 0");
+        if (o->c && !finite_pos(o->c[b]))
+            return fail(UMI_ERR_INVALID_ARG, "per-curve c must be finite and > 0");
+    }
+    return UMI_OK;
+}
+
 // Checks curves at explicit offsets: lengths >= 0, valid windows, ranges
 // pairwise disjoint.  `span` gets max(off + len), `total` the sample count.
 umi_status check_curves(const int64_t* offsets, const int64_t* lengths, int64_t n,
@@ -169,7 +188,7 @@ struct Packed {
 };
 
 umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
-                const umi_launch& opt, Packed* out)
+                float alpha, float c, const umi_options& o, const umi_launch& opt, Packed* out)
 {
     std::vector<int> tile_of((size_t)n);
     std::vector<int32_t> order;
@@ -201,6 +220,8 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
         d.W = W[b];
         d.tile = tile_of[(size_t)b];
         d.tile_base = (int32_t)out->ntiles;
+        d.alpha = o.alpha ? o.alpha[b] : alpha;
+        d.c = o.c ? o.c[b] : c;
         out->curve_tiles[i] = nt;
         out->ntiles += nt;
     }
@@ -218,14 +239,14 @@ size_t block_bytes(int64_t ncurves)
     return sizeof(BatchHeader) + (size_t)ncurves * sizeof(CurveDesc);
 }
 
-void write_block(uint8_t* dst, const Packed& p, float alpha, float c, int32_t iters)
+void write_block(uint8_t* dst, const Packed& p, int32_t iters, const umi_options& o)
 {
     BatchHeader h = {};
     h.n_curves = (int32_t)p.curves.size();
     h.n_tiles = (int32_t)p.ntiles;
-    h.alpha = alpha;
-    h.c = c;
     h.iters = iters;
+    h.scale = o.scale;
+    h.detrended = o.detrended;
     std::memcpy(dst, &h, sizeof h);
     if (!p.curves.empty())
         std::memcpy(dst + sizeof h, p.curves.data(), p.curves.size() * sizeof(CurveDesc));
@@ -410,7 +431,8 @@ int cu_count(int device)
 umi_status detrend_gather(const float* flux, const double* time, const int64_t* offsets,
                           const int64_t* lengths, int64_t n_curves, const int32_t* W,
                           float alpha, float c, int32_t iters, float* trend, float* median,
-                          const umi_launch* launch, hipStream_t stream)
+                          const umi_options* options, const umi_launch* launch,
+                          hipStream_t stream)
 {
     umi_status st;
     if (take_injected(&st)) return st;
@@ -422,13 +444,15 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     umi_launch opt;
     if ((st = check_launch(launch, &opt)) != UMI_OK) return st;
     if ((st = check_params(alpha, c, iters)) != UMI_OK) return st;
+    umi_options o;
+    if ((st = check_options(options, n_curves, &o)) != UMI_OK) return st;
     int64_t span, total;
     if ((st = check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK) return st;
     if (total == 0) return UMI_OK;
     if (!flux || !trend) return fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
 
     Packed p;
-    if ((st = pack(offsets, lengths, n_curves, W, opt, &p)) != UMI_OK) return st;
+    if ((st = pack(offsets, lengths, n_curves, W, alpha, c, o, opt, &p)) != UMI_OK) return st;
     const int64_t nc = (int64_t)p.curves.size();
 
     int device = 0;
@@ -443,7 +467,7 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
             return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
-    write_block(ws->hblock, p, alpha, c, iters);
+    write_block(ws->hblock, p, iters, o);
     if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return fail_hip(e, "curve table copy");
@@ -516,7 +540,7 @@ umi_status umi_detrend(const float* flux, const double* time, int64_t n, int32_t
     const int64_t off = 0, len = n;
     const int32_t w = W;
     return umi::detrend_gather(flux, time, &off, &len, 1, &w, alpha, c, iters, trend, median,
-                               nullptr, static_cast<hipStream_t>(stream));
+                               nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 umi_status umi_detrend_batch(const float* flux, const double* time, const int64_t* lengths,
@@ -533,7 +557,7 @@ umi_status umi_detrend_batch(const float* flux, const double* time, const int64_
         if (lengths[b] > 0) acc += lengths[b];
     }
     return umi::detrend_gather(flux, time, off.data(), lengths, n_curves, W, alpha, c, iters,
-                               trend, median, launch, static_cast<hipStream_t>(stream));
+                               trend, median, nullptr, launch, static_cast<hipStream_t>(stream));
 }
 
 umi_status umi_detrend_gather(const float* flux, const double* time, const int64_t* offsets,
@@ -542,7 +566,30 @@ umi_status umi_detrend_gather(const float* flux, const double* time, const int64
                               const umi_launch* launch, void* stream)
 {
     return umi::detrend_gather(flux, time, offsets, lengths, n_curves, W, alpha, c, iters, trend,
-                               median, launch, static_cast<hipStream_t>(stream));
+                               median, nullptr, launch, static_cast<hipStream_t>(stream));
+}
+
+umi_status umi_detrend_gather_ex(const float* flux, const double* time, const int64_t* offsets,
+                                 const int64_t* lengths, int64_t n_curves, const int32_t* W,
+                                 float alpha, float c, int32_t iters, float* trend,
+                                 float* median, const umi_options* options,
+                                 const umi_launch* launch, void* stream)
+{
+    if (offsets) {
+        return umi::detrend_gather(flux, time, offsets, lengths, n_curves, W, alpha, c, iters,
+                                   trend, median, options, launch,
+                                   static_cast<hipStream_t>(stream));
+    }
+    if (n_curves > 0 && !lengths)
+        return umi::fail(UMI_ERR_INVALID_ARG, "lengths must not be NULL");
+    std::vector<int64_t> off(n_curves > 0 ? (size_t)n_curves : 0);
+    int64_t acc = 0;
+    for (int64_t b = 0; b < n_curves; ++b) {
+        off[(size_t)b] = acc;
+        if (lengths[b] > 0) acc += lengths[b];
+    }
+    return umi::detrend_gather(flux, time, off.data(), lengths, n_curves, W, alpha, c, iters,
+                               trend, median, options, launch, static_cast<hipStream_t>(stream));
 }
 
 umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves, int32_t max_W,
@@ -602,8 +649,9 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
     return UMI_OK;
 }
 
-umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* lengths,
-                        const int32_t* W, int64_t n_curves, float alpha, float c, int32_t iters)
+umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* lengths,
+                           const int32_t* W, int64_t n_curves, float alpha, float c,
+                           int32_t iters, const umi_options* options)
 {
     umi_status st;
     if (umi::take_injected(&st)) return st;
@@ -613,6 +661,8 @@ umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* leng
     if (n_curves > 0 && (!offsets || !lengths || !W))
         return umi::fail(UMI_ERR_INVALID_ARG, "offsets, lengths and W must not be NULL");
     if ((st = umi::check_params(alpha, c, iters)) != UMI_OK) return st;
+    umi_options o;
+    if ((st = umi::check_options(options, n_curves, &o)) != UMI_OK) return st;
     int64_t span = 0, total = 0;
     if (n_curves > 0 &&
         (st = umi::check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK)
@@ -623,7 +673,8 @@ umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* leng
         if (W[b] > p->max_W) return umi::fail(UMI_ERR_INVALID_ARG, "W above the plan's max_W");
     const umi_launch opt = {UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
     umi::Packed pk;
-    if (n_curves > 0 && (st = umi::pack(offsets, lengths, n_curves, W, opt, &pk)) != UMI_OK)
+    if (n_curves > 0 &&
+        (st = umi::pack(offsets, lengths, n_curves, W, alpha, c, o, opt, &pk)) != UMI_OK)
         return st;
     if (pk.ntiles > p->max_tiles)
         return umi::fail(UMI_ERR_UNSUPPORTED, "batch needs more tiles than the plan holds");
@@ -636,7 +687,7 @@ umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* leng
             return umi::fail_hip(e, "hipEventSynchronize");
         s.pending = false;
     }
-    umi::write_block(s.host, pk, alpha, c, iters);
+    umi::write_block(s.host, pk, iters, o);
     if (!s.exec) {
         // capture once per slot: copy of the staged block, pre-pass over
         // max_curves (blocks beyond the batch exit), persistent estimate
@@ -667,6 +718,12 @@ umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* leng
     s.pending = true;
     p->next ^= 1;
     return UMI_OK;
+}
+
+umi_status umi_plan_run(umi_plan* p, const int64_t* offsets, const int64_t* lengths,
+                        const int32_t* W, int64_t n_curves, float alpha, float c, int32_t iters)
+{
+    return umi_plan_run_ex(p, offsets, lengths, W, n_curves, alpha, c, iters, nullptr);
 }
 
 umi_status umi_plan_destroy(umi_plan* p)
@@ -736,7 +793,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.3.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.4.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

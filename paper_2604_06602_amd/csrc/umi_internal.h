@@ -24,10 +24,10 @@ constexpr double kGapDays = 0.5;             // segment break threshold (days)
 struct BatchHeader {
     int32_t n_curves;   // entries in the curve table
     int32_t n_tiles;    // tiles over all curves
-    float alpha;        // asymmetry factor (Eq. 2)
-    float c;            // bisquare tuning constant
     int32_t iters;      // Phase 3 iterations
-    int32_t pad[3];
+    int32_t scale;      // umi_scale: Phase 2 estimator
+    float* detrended;   // flux / trend output (curve offsets as for trend), or null
+    int64_t pad;
 };
 static_assert(sizeof(BatchHeader) == 32, "BatchHeader layout");
 
@@ -38,8 +38,10 @@ struct CurveDesc {
     int32_t W;          // window (odd)
     int32_t tile;       // output positions per tile
     int32_t tile_base;  // index of this curve's first tile in the tile list
+    float alpha;        // asymmetry factor (Eq. 2) of this curve
+    float c;            // bisquare tuning constant of this curve
 };
-static_assert(sizeof(CurveDesc) == 24, "CurveDesc layout");
+static_assert(sizeof(CurveDesc) == 32, "CurveDesc layout");
 
 // Segment record written by the pre-pass at segtab[curve.off + segment id]:
 //   x = first valid index, y = last valid index (curve-local),

@@ -30,6 +30,7 @@
 
 #include <stdint.h>
 
+#include "umi.h"
 #include "umi_internal.h"
 
 // Every fused multiply-add below is written out with __builtin_fmaf; the
@@ -496,14 +497,51 @@ __device__ __forceinline__ void upper_ssq_multi(const float* __restrict__ x, int
     }
 }
 
+// The j-th smallest value (0-based) of the window held at compacted
+// positions [ca, cb), from the wavelet matrix and the sorted tile.
+__device__ __forceinline__ float window_value(const MainSmem& sm, int levels, uint32_t ca,
+                                              uint32_t cb, uint32_t j)
+{
+    return key_value((uint32_t)(sm.sortbuf[wavelet_kth(sm, levels, ca, cb, j)] >> 32));
+}
+
+// Scale ablation: the standard MAD, the lower median of |x - m| over a window
+// of n samples with median m.  With the window sorted (v_0 <= ... <= v_{n-1})
+// and m = v_q, q = (n-1)/2, the q+1 smallest deviations belong to a run
+// v_lo .. v_{lo+q} with 0 <= lo <= q, so the q-th smallest deviation is the
+// minimum over lo of max(m - v_lo, v_{lo+q} - m).  The first term falls and
+// the second rises with lo: a binary search finds where they cross.  Float
+// subtraction is monotone, so the result is the exact MAD rounded once.
+__device__ __forceinline__ float window_mad(const MainSmem& sm, int levels, uint32_t ca,
+                                         uint32_t n, float m)
+{
+    const uint32_t cb = ca + n;
+    const uint32_t q = (n - 1) >> 1;
+    uint32_t lo = 0, hi = q;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const float below = m - window_value(sm, levels, ca, cb, mid);
+        const float above = window_value(sm, levels, ca, cb, mid + q) - m;
+        if (below <= above)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    float mad = window_value(sm, levels, ca, cb, lo + q) - m;
+    if (lo > 0) mad = __builtin_fminf(mad, m - window_value(sm, levels, ca, cb, lo - 1));
+    return mad;
+}
+
 // The windows of one tile: each lane takes R consecutive output positions.
 template <int R>
 __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int nv,
                                              const CurveDesc& cd, int h, int s0, int t0, int t1,
                                              const int32_t* __restrict__ segid,
                                              const int4* __restrict__ segtab, float alpha,
-                                             float c, int iters, float* __restrict__ trend,
-                                             float* __restrict__ median)
+                                             float c, int iters, int scale,
+                                             float* __restrict__ trend,
+                                             float* __restrict__ median,
+                                             float* __restrict__ detrended)
 {
     const int m_min = max(1, cd.W / 3);
     const int pfirst = t0 + (int)threadIdx.x * R;
@@ -537,33 +575,44 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
     for (int r = 1; r < R; ++r) mine = mine && live[r] && n[r] == n_u && ca[r] == ca[0] + r;
     const bool uniform = __all(mine);
 
-    // Phase 1 (median) and the count of points above it, per window
-    float m[R];
+    // Phase 1 (median) and Phase 2 (Eq. 1, or the MAD ablation) per window
+    float m[R], sc[R];
     uint32_t nplus[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         m[r] = 0.0f;
+        sc[r] = 0.0f;
         nplus[r] = 0;
         if (live[r]) {
             const uint32_t cb = ca[r] + n[r];
             const uint32_t rk = wavelet_kth(sm, levels, ca[r], cb, (n[r] - 1) >> 1);
             m[r] = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
-            // the points strictly above m are the window's elements ranked
-            // after the last tile element numerically equal to m (ties and
-            // -0/+0 sit next to m in the sorted order)
-            uint32_t rh = rk;
-            while (rh + 1 < (uint32_t)nv && key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m[r])
-                ++rh;
-            nplus[r] = n[r] - wavelet_count_less(sm, levels, ca[r], cb, rh + 1);
+            if (scale == UMI_SCALE_MAD) {
+                sc[r] = window_mad(sm, levels, ca[r], n[r], m[r]);
+            } else {
+                // the points strictly above m are the window's elements ranked
+                // after the last tile element numerically equal to m (ties and
+                // -0/+0 sit next to m in the sorted order)
+                uint32_t rh = rk;
+                while (rh + 1 < (uint32_t)nv &&
+                       key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m[r])
+                    ++rh;
+                nplus[r] = n[r] - wavelet_count_less(sm, levels, ca[r], cb, rh + 1);
+            }
         }
     }
-    // Phase 2 (Eq. 1)
-    float ssq[R];
-    if (uniform) {
-        upper_ssq_multi<R>(sm.xv + ca[0], (int)n_u, m, ssq);
-    } else {
+    if (scale != UMI_SCALE_MAD) {
+        float ssq[R];
+        if (uniform) {
+            upper_ssq_multi<R>(sm.xv + ca[0], (int)n_u, m, ssq);
+        } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) ssq[r] = live[r] ? upper_ssq(sm.xv, (int)ca[r], (int)n[r], m[r]) : 0.0f;
+            for (int r = 0; r < R; ++r)
+                ssq[r] = live[r] ? upper_ssq(sm.xv, (int)ca[r], (int)n[r], m[r]) : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (nplus[r] > 0) sc[r] = kScaleConst * __builtin_sqrtf(ssq[r] / (float)nplus[r]);
     }
     float k[R], mu[R];
     bool act[R];
@@ -572,10 +621,9 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         mu[r] = m[r];
         k[r] = 0.0f;
         act[r] = false;
-        if (live[r] && nplus[r] > 0 && iters > 0) {
-            const float s = kScaleConst * __builtin_sqrtf(ssq[r] / (float)nplus[r]);
-            const float kk = 1.0f / (c * s);
-            if (s > 0.0f && isfinite(kk)) {
+        if (live[r] && sc[r] > 0.0f && iters > 0) {
+            const float kk = 1.0f / (c * sc[r]);
+            if (isfinite(kk)) {
                 k[r] = kk;
                 act[r] = true;
             }
@@ -602,6 +650,13 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         if (p < t1) {
             trend[cd.off + p] = live[r] ? mu[r] : nanf_;
             if (median) median[cd.off + p] = live[r] ? m[r] : nanf_;
+            if (detrended) {
+                // normalisation stage: flux / trend (a live sample is valid,
+                // so its compacted position is its rank among valid ones)
+                float d = nanf_;
+                if (live[r]) d = sm.xv[rank1(sm.vbits, sm.vpre, (uint32_t)(p - s0))] / mu[r];
+                detrended[cd.off + p] = d;
+            }
         }
     }
 }
@@ -617,9 +672,9 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const int wave = tid >> 6;
-    const float alpha = hdr->alpha;
-    const float c = hdr->c;
     const int iters = hdr->iters;
+    const int scale = hdr->scale;
+    float* const detrended = hdr->detrended;
     // tile range [tile_first, tile_end): a count < 0 means "all tiles of the batch"
     const int tile_end = tile_count < 0 ? hdr->n_tiles : tile_first + tile_count;
 
@@ -633,6 +688,8 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 
         const int2 td = tiles[tile];
         const CurveDesc cd = curves[td.x];
+        const float alpha = cd.alpha;
+        const float c = cd.c;
         const int h = (cd.W - 1) >> 1;
         const int t0 = td.y;
         const int t1 = min(t0 + cd.tile, cd.len);
@@ -730,11 +787,14 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         // --- the tile's windows: R consecutive positions per lane ---
         const int R = (t1 - t0 + kMainThreads - 1) / kMainThreads;  // tile <= kMaxTile -> R <= 3
         if (R == 3)
-            tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
+            tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+                            trend, median, detrended);
         else if (R == 2)
-            tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
+            tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+                            trend, median, detrended);
         else
-            tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, trend, median);
+            tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+                            trend, median, detrended);
         __syncthreads();
     }
 }

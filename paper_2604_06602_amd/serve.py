@@ -8,8 +8,9 @@ A scheduler thread
     (flux, time, trend) plus the plan's per-sample workspace, and every
     admission group (the requests admitted together) gets one contiguous
     range of it, filled by a single host-to-device copy on a copy stream;
-  * launches steps: all admitted, not yet launched groups that share
-    (alpha, c, iters) go into one batch, run through a replayable plan (a
+  * launches steps: all admitted, not yet launched groups that share the
+    iteration count go into one batch -- each curve keeps its own alpha and
+    c (the Table 4 settings mix freely) -- run through a replayable plan (a
     captured hipGraph of the tile-table copy, the segmentation pre-pass and
     the persistent estimate kernel) on the compute stream.  Up to two steps
     are in flight, so requests that arrive while one step runs are uploaded
@@ -118,7 +119,9 @@ class Request:
 
     @property
     def key(self):
-        return (self.alpha, self.c, self.iters)
+        # alpha and c travel per curve (Table 4 settings mix in one step);
+        # the iteration count is per launch
+        return self.iters
 
 
 @dataclass
@@ -298,14 +301,14 @@ class GpuExecutor:
     def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
         return self.stage_upload(offset, [(flux, time)])
 
-    def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+    def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
         """Run one batch; then copy each (offset, size) range of the trend back."""
         torch = self.torch
         for ev, _, _ in uploads:
             self.compute_stream.wait_event(ev)
-        alpha, c, iters = key
         try:
-            self.plan.run(offsets, lengths, Ws, alpha, c, iters)
+            self.plan.run(offsets, lengths, Ws, np.asarray(alphas, np.float32),
+                          np.asarray(cs, np.float32), iters)
         except Exception:
             # the step never ran: its uploads' staging is free once copied
             for ev, tok, _ in uploads:
@@ -368,14 +371,13 @@ class FakeExecutor:
         self.time[offset:offset + flux.size] = time
         return None
 
-    def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+    def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
         k = next(self._step)
         if self.fail_when is not None:
             self.fail_when(k, len(offsets))
-        alpha, c, iters = key
         trend = np.full(self.capacity, np.nan, np.float32)
-        for o, L, W in zip(offsets, lengths, Ws):
-            trend[o:o + L] = self.fn(self.flux[o:o + L], self.time[o:o + L], W, alpha, c, iters)
+        for o, L, W, a, c in zip(offsets, lengths, Ws, alphas, cs):
+            trend[o:o + L] = self.fn(self.flux[o:o + L], self.time[o:o + L], W, a, c, iters)
         outs = [trend[o:o + s].copy() for o, s in ranges]
         return (_time.perf_counter() + self.delay, outs)
 
@@ -532,7 +534,8 @@ class Server:
             r.launched = now
         try:
             step.handle = self.ex.launch([r.offset for r in reqs], [r.n for r in reqs],
-                                         [r.W for r in reqs], step.groups[0].key,
+                                         [r.W for r in reqs], [r.alpha for r in reqs],
+                                         [r.c for r in reqs], step.groups[0].key,
                                          [g.upload for g in step.groups if g.upload is not None],
                                          [(g.offset, g.size) for g in step.groups])
             step.launched_at = now

@@ -140,6 +140,41 @@ def test_gather_validation_without_device(lib):
                                       None, None) == 0
 
 
+def test_options_validation_without_device(lib):
+    """umi_options: per-curve alpha/c must be finite and > 0, the scale known,
+    reserved zero; all checked before anything touches the device."""
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    L = np.asarray([10, 20], np.int64)
+    w = np.asarray([5, 7], np.int32)
+
+    def call(alpha=None, c=None, scale=0, reserved=0, offsets=None):
+        a = None if alpha is None else np.asarray(alpha, np.float32)
+        cc = None if c is None else np.asarray(c, np.float32)
+        o = lib.Options(None if a is None else a.ctypes.data, None if cc is None else cc.ctypes.data,
+                        scale, reserved, None)
+        offs = None if offsets is None else np.asarray(offsets, np.int64)
+        lib.debug_inject_error(0)
+        return lib.lib.umi_detrend_gather_ex(
+            ctypes.c_void_p(1), None, None if offs is None else offs.ctypes.data_as(i64),
+            L.ctypes.data_as(i64), L.size, w.ctypes.data_as(i32), 2.0, 5.0, 5,
+            ctypes.c_void_p(1), None, ctypes.byref(o), None, None)
+    assert call(alpha=[2.0, 0.0]) == 1
+    assert call(alpha=[2.0, float("nan")]) == 1
+    assert call(c=[-5.0, 5.0]) == 1
+    assert call(c=[5.0, float("inf")]) == 1
+    assert call(scale=2) == 1
+    assert call(scale=-1) == 1
+    assert call(reserved=1) == 1
+    assert call(alpha=[2.0, 3.0], offsets=[0, 5]) == 1    # overlapping explicit offsets
+    with pytest.raises(ValueError):
+        lib._options(2, [2.0], 5.0, "upper_rms", None)    # wrong per-curve count
+    with pytest.raises(ValueError):
+        lib._options(2, 2.0, 5.0, "iqr", None)
+    assert lib._options(2, 2.0, 5.0, "upper_rms", None)[0] is None  # plain call suffices
+    assert lib.lib.umi_plan_run_ex(None, None, None, None, 0, 2.0, 5.0, 5, None) == 1
+
+
 def test_plan_validation_without_device(lib):
     h = ctypes.c_void_p()
     # no stream: graph capture needs a non-default stream

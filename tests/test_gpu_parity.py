@@ -136,7 +136,9 @@ def test_config1_full_size_sampled(torch, umi, oracle_lib):
     assert np.isfinite(g_tr).sum() == 1000 * (18000 - 720)
 
 
-def test_edge_cases(torch, umi, oracle_lib):
+def edge_case_batch():
+    """Empty, tiny, all-invalid, dead-segment, invalid-time, tied, signed-zero,
+    constant, negative, large-offset, W=1, sparse and largest-W curves."""
     rng = np.random.default_rng(5)
     dt = 2 / 1440
     curves = []
@@ -166,7 +168,11 @@ def test_edge_cases(torch, umi, oracle_lib):
     f = rng.normal(1, 1e-3, 5000); f[rng.random(5000) < 0.3] = np.nan
     add(f, np.arange(5000) * dt, 361)                              # many isolated NaNs
     add(rng.normal(1, 1e-3, 4100), np.arange(4100) * dt, 2047)     # largest W
-    packed = synth.lightcurves.pack([(c[0], c[1] if c[1] is not None else np.arange(c[0].size) * dt, c[2]) for c in curves])
+    return synth.lightcurves.pack([(c[0], c[1] if c[1] is not None else np.arange(c[0].size) * dt, c[2]) for c in curves])
+
+
+def test_edge_cases(torch, umi, oracle_lib):
+    packed = edge_case_batch()
     mag = window_magnitude(packed.flux, packed.time, packed.lengths, packed.W, oracle_lib)
     for a, c, it in [(2.0, 5.0, 5), (1.0, 5.0, 5), (10.0, 2.5, 5), (0.5, 5.0, 3), (2.0, 5.0, 0), (3.0, 5.0, 1)]:
         g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths, packed.W,

@@ -1,9 +1,10 @@
 """GPU serving: continuous batching through the replayable plan.
 
-Curves drawn like the mixed workload arrive while earlier ones run; every
-result must be bit-identical to the same curve run alone through the C ABI,
-and sampled positions must match the FP64 oracle (median-independent check
-of the trend at 1e-5 relative).
+Curves drawn like the mixed workload arrive while earlier ones run, each
+with one of the Table 4 (alpha, c) settings, so steps mix them; every result
+must be bit-identical to the same curve run alone through the C ABI with its
+own setting, and sampled positions must match the FP64 oracle (trend at
+1e-5 relative).
 """
 from __future__ import annotations
 
@@ -30,32 +31,33 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
     from paper_2604_06602_amd.serve import GpuExecutor, Server
 
     rng = np.random.default_rng(4)
+    presets = [(2.0, 5.0), (3.0, 5.0), (1.0, 5.0), (10.0, 2.5)]
     curves = []
     for i in range(60):
         f, t, W = synth.curve_for(4, i)
         L = min(f.size, 30000)
-        curves.append((f[:L], t[:L], W))
-    total = sum(f.size for f, _, _ in curves)
+        curves.append((f[:L], t[:L], W) + presets[i % 4])
+    total = sum(cv[0].size for cv in curves)
     ex = GpuExecutor(capacity=total // 2, max_curves=64, max_W=721)  # budget forces queueing
     srv = Server(ex)
     futs = []
-    for i, (f, t, W) in enumerate(curves):
-        futs.append(srv.submit(f, t, W))
+    for i, (f, t, W, a, c) in enumerate(curves):
+        futs.append(srv.submit(f, t, W, alpha=a, c=c))
         if i % 10 == 9:  # bursts of ten: later arrivals find earlier ones on the GPU
             time.sleep(float(rng.exponential(0.002)))
     results = [fu.result(timeout=120) for fu in futs]
     summary = srv.summary()
     srv.close()
     assert summary["completed"] == len(curves) and summary["steps"] < len(curves)
-    for (f, t, W), res in zip(curves, results):
+    for (f, t, W, a, c), res in zip(curves, results):
         fd = torch.from_numpy(f).cuda()
         td = torch.from_numpy(t).cuda()
-        alone, _ = umi.detrend(fd, td, W)
+        alone, _ = umi.detrend(fd, td, W, alpha=a, c=c)
         torch.cuda.synchronize()
         assert np.array_equal(alone.cpu().numpy().view(np.uint32), res.view(np.uint32))
-    for (f, t, W), res in list(zip(curves, results))[:6]:
+    for (f, t, W, a, c), res in list(zip(curves, results))[:8]:
         idx = np.unique(rng.integers(0, f.size, 40))
-        o_tr, _ = oracle_lib.detrend_at(f, t, W, idx)
+        o_tr, _ = oracle_lib.detrend_at(f, t, W, idx, alpha=a, c=c)
         ok = ~np.isnan(o_tr)
         assert np.array_equal(np.isnan(res[idx]), ~ok)
         rel = np.abs(res[idx][ok] - o_tr[ok]) / np.abs(o_tr[ok])

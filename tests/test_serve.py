@@ -156,25 +156,34 @@ def test_failed_step_fails_only_its_requests():
     assert s["failed"] == 1 and s["completed"] == 2
 
 
-def test_parameters_never_share_a_step():
+def test_presets_share_steps_iteration_counts_do_not():
+    """Per-curve alpha and c (Table 4) mix in one step and each curve gets its
+    own pair; requests with another iteration count run in other steps."""
     seen = []
 
     def record(f, t, W, a, c, it):
         seen.append((a, c, it))
-        return f.copy()
+        return f * np.float32(a) + np.float32(c)
 
     class Recording(FakeExecutor):
-        def launch(self, offsets, lengths, Ws, key, uploads, ranges):
-            steps.append(key)
-            return super().launch(offsets, lengths, Ws, key, uploads, ranges)
+        def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
+            steps.append((len(offsets), iters))
+            return super().launch(offsets, lengths, Ws, alphas, cs, iters, uploads, ranges)
     steps = []
-    srv = Server(Recording(100000, fn=record, delay=0.005))
-    futs = [srv.submit(np.ones(50, np.float32), W=5, alpha=a) for a in [2.0, 1.0, 2.0, 1.0, 10.0]]
-    for fu in futs:
-        fu.result(timeout=5)
+    srv = Server(Recording(100000, fn=record, delay=0.02), max_inflight=1)
+    first = srv.submit(np.ones(50, np.float32), W=5)          # occupies the device
+    time.sleep(0.005)
+    presets = [(2.0, 5.0), (3.0, 5.0), (1.0, 5.0), (10.0, 2.5)]
+    futs = [srv.submit(np.ones(50, np.float32), W=5, alpha=a, c=c) for a, c in presets]
+    other = srv.submit(np.ones(50, np.float32), W=5, iters=3)
+    first.result(timeout=5)
+    for (a, c), fu in zip(presets, futs):
+        assert (fu.result(timeout=5) == np.float32(a) + np.float32(c)).all()
+    other.result(timeout=5)
     srv.close()
-    assert sorted(set(seen)) == sorted(set((a, 5.0, 5) for a in [2.0, 1.0, 10.0]))
-    assert len(steps) >= 3
+    assert (4, 5) in steps or any(n >= 2 and it == 5 for n, it in steps[1:])
+    assert all(it in (3, 5) for _, it in steps)
+    assert sorted(set(seen)) == sorted(set([(a, c, 5) for a, c in presets] + [(2.0, 5.0, 3)]))
 
 
 def test_latency_is_measured_from_scheduled_arrival():
@@ -189,9 +198,9 @@ def test_latency_is_measured_from_scheduled_arrival():
 
 def test_admission_groups_respect_the_step_limit():
     class Checking(FakeExecutor):
-        def launch(self, offsets, lengths, Ws, key, uploads, ranges):
+        def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
             assert len(offsets) <= 7
-            return super().launch(offsets, lengths, Ws, key, uploads, ranges)
+            return super().launch(offsets, lengths, Ws, alphas, cs, iters, uploads, ranges)
     gate = threading.Event()
     srv = Server(Checking(100000, delay=0.001), max_step_curves=7)
     futs = [srv.submit(np.ones(20, np.float32), W=5) for _ in range(50)]
