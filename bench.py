@@ -110,6 +110,43 @@ def counted_traffic():
         return None
 
 
+def measured_fma_peak(torch, stream, log, iters=40000, launches=10):
+    """Sustained scalar FP32 FMA rate of this GPU (TFLOP/s): the measurement
+    aid in libumi_diag.so (16 independent FMA chains per thread, 8 waves per
+    SIMD, packed forms disabled as for the library), timed with HIP events on
+    `stream`."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2604_06602_amd", "libumi_diag.so")
+    lib = ctypes.CDLL(path)
+    lib.umi_diag_fma_peak.restype = ctypes.c_int32
+    lib.umi_diag_fma_peak.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    grid = cus * 8  # 8 workgroups of 4 waves per CU: 8 waves per SIMD
+    out = torch.empty(grid * 256, dtype=torch.float32, device="cuda")
+    flop = ctypes.c_double()
+    h = ctypes.c_void_p(int(stream.cuda_stream))
+
+    def launch():
+        st = lib.umi_diag_fma_peak(iters, grid, ctypes.c_void_p(out.data_ptr()), h,
+                                   ctypes.byref(flop))
+        if st != 0:
+            raise RuntimeError("umi_diag_fma_peak failed (%d)" % st)
+    for _ in range(3):
+        launch()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(launches):
+        launch()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / launches
+    tf = flop.value / (ms * 1e-3) / 1e12
+    log("measured scalar FP32 FMA peak: %.1f TFLOP/s (%.3f ms per launch)" % (tf, ms))
+    return tf
+
+
 SERVE_POOL = 1000  # distinct curves drawn like the mixed workload, cycled by arrivals
 
 
@@ -293,6 +330,7 @@ def main(argv=None):
     achieved = flop_launch / (main_ms * 1e-3) / 1e12
     log("step %.3f ms (main %.3f ms), wall %.3f s" % (ms_step, main_ms, wall))
     log("main kernel per step (ms): " + " ".join("%.3f" % v for v in main_each))
+    fma_peak = measured_fma_peak(torch, stream, log)
 
     per_curve = None
     if args.compare_per_curve:
@@ -340,7 +378,9 @@ def main(argv=None):
                      "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                      "avg_launch_ms": main_ms, "flop_per_launch": flop_launch,
                      "window_samples_per_launch": window_samples,
-                     "flop_per_window_sample": 3 + 8 * iters},
+                     "flop_per_window_sample": 3 + 8 * iters,
+                     "measured_fma_peak": fma_peak,
+                     "frac_of_measured_fma_peak": achieved / fma_peak},
     }
     if per_curve is not None:
         out["comparison"] = per_curve

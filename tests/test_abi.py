@@ -212,3 +212,22 @@ def test_autotune_candidates():
     for W in [25, 121, 361, 721, 1441]:
         c = autotune.tile_candidates(W)
         assert autotune.default_tile(W) in c and max(c) == autotune.max_tile(W)
+
+
+def test_diag_library_exports_its_header():
+    """The measurement aid (include/umi_diag.h) loads and rejects bad
+    arguments before launching anything."""
+    text = open(os.path.join(ROOT, "include", "umi_diag.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(umi_[a-z_]+)\s*\(", text)))
+    assert names == ["umi_diag_fma_peak"]
+    diag = ctypes.CDLL(os.path.join(ROOT, "paper_2604_06602_amd", "libumi_diag.so"))
+    for n in names:
+        assert hasattr(diag, n), n
+    f = diag.umi_diag_fma_peak
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_double)]
+    assert f(0, 8, ctypes.c_void_p(1), None, None) == 1
+    assert f(10, 0, ctypes.c_void_p(1), None, None) == 1
+    assert f(10, 8, None, None, None) == 1
