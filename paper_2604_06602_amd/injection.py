@@ -51,22 +51,26 @@ def percent_error(recovered: float, depth_ppm: float) -> float:
     return abs(recovered - d) / d * 100.0
 
 
-def _batch(mission, n_stars, depth_ppm, first=0):
+def _batch(mission, n_stars, depth_ppm, first=0, duration_d=None, W=None):
     from synth import injection as si
-    curves = [si.injected(mission, first + i, depth_ppm) for i in range(n_stars)]
+    kw = {} if duration_d is None else {"duration_d": duration_d}
+    curves = [si.injected(mission, first + i, depth_ppm, **kw) for i in range(n_stars)]
     flux = np.concatenate([c[0] for c in curves])
     time = np.concatenate([c[1] for c in curves])
     lengths = np.array([c[0].size for c in curves], np.int64)
-    W = np.array([c[2] for c in curves], np.int32)
+    W = np.array([c[2] if W is None else W for c in curves], np.int32)
     masks = [c[3] for c in curves]
     return flux, time, lengths, W, masks
 
 
-def run(mission: str, n_stars: int, depths=None, methods=None, first: int = 0, detrend=None):
+def run(mission: str, n_stars: int, depths=None, methods=None, first: int = 0, detrend=None,
+        duration_d=None, W=None):
     """Median per-star absolute % depth error for each method and depth.
 
     ``detrend(flux, time, lengths, W, alpha, c, scale) -> detrended flux`` (host
-    arrays) defaults to the GPU library; tests may pass another one."""
+    arrays) defaults to the GPU library; tests may pass another one.
+    ``duration_d`` overrides the 3-hour transit duration and ``W`` the
+    mission's window (e.g. the window of a longer ``window_length``)."""
     from synth import injection as si
     depths = si.DEPTHS_PPM if depths is None else depths
     methods = METHODS if methods is None else methods
@@ -74,10 +78,10 @@ def run(mission: str, n_stars: int, depths=None, methods=None, first: int = 0, d
     table = {m: {} for m in methods}
     errors = {m: {} for m in methods}
     for d in depths:
-        flux, time, lengths, W, masks = _batch(mission, n_stars, d, first)
+        flux, time, lengths, Ws, masks = _batch(mission, n_stars, d, first, duration_d, W)
         off = np.concatenate([[0], np.cumsum(lengths)])
         for name, p in methods.items():
-            det = detrend(flux, time, lengths, W, p["alpha"], p["c"], p["scale"])
+            det = detrend(flux, time, lengths, Ws, p["alpha"], p["c"], p["scale"])
             errs = [percent_error(recovered_depth(det[off[i]:off[i + 1]], masks[i]), d)
                     for i in range(len(masks))]
             errors[name][d] = errs

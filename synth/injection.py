@@ -66,9 +66,10 @@ def in_transit(t, epoch, period=PERIOD_D, duration=DURATION_D):
     return ph < duration
 
 
-def injected(mission: str, i: int, depth_ppm: float):
+def injected(mission: str, i: int, depth_ppm: float, duration_d: float = DURATION_D,
+             period_d: float = PERIOD_D):
     """(flux float32 with the transits multiplied in, time, W, in-transit mask)."""
     f, t, W, epoch = star(mission, i)
-    mask = in_transit(t, epoch)
+    mask = in_transit(t, epoch, period_d, duration_d)
     g = f * np.where(mask, 1.0 - depth_ppm * 1e-6, 1.0)
     return g.astype(np.float32), t, W, mask

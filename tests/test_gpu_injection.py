@@ -50,3 +50,21 @@ def test_errors_fall_with_depth_above_the_noise(tables):
     for mission, table in tables.items():
         for m, row in table.items():
             assert row[1000] < row[200] < row[50], (mission, m, row)
+
+
+def test_long_transits_need_a_longer_window():
+    """Section 4.2: with the 0.5-day window (W = 361 at 2 min) the depth of a
+    transit longer than about 5 hours is underestimated; a 1.5-day
+    window_length (W = 1081 by the rule of Section 2) recovers a 10-hour
+    transit far better."""
+    from paper_2604_06602_amd import _lib
+    from paper_2604_06602_amd import injection as inj
+    W_long = _lib.window_from_cadence(2 / 1440, 1.5)
+    assert W_long == 1081
+    default = {"umi_default": inj.METHODS["umi_default"]}
+    short, _ = inj.run("tess", 200, depths=(1000,), methods=default, duration_d=10 / 24)
+    long_, _ = inj.run("tess", 200, depths=(1000,), methods=default, duration_d=10 / 24,
+                       W=W_long)
+    three_h, _ = inj.run("tess", 200, depths=(1000,), methods=default)
+    assert short["umi_default"][1000] > 2 * long_["umi_default"][1000]
+    assert short["umi_default"][1000] > 2 * three_h["umi_default"][1000]
