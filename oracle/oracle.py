@@ -84,16 +84,16 @@ def _load():
         lib.umi_oracle_detrend_ex.restype = ctypes.c_int
         lib.umi_oracle_detrend_ex.argtypes = [_f32p, _f64p, ctypes.c_int64, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                              ctypes.c_int, _f64p, _f32p]
+                                              ctypes.c_int, ctypes.c_double, _f64p, _f32p]
         lib.umi_oracle_detrend_at_ex.restype = ctypes.c_int
         lib.umi_oracle_detrend_at_ex.argtypes = [_f32p, _f64p, ctypes.c_int64, ctypes.c_int,
                                                  ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                                 ctypes.c_int, _i64p, ctypes.c_int64, _f64p,
-                                                 _f32p]
+                                                 ctypes.c_int, ctypes.c_double, _i64p,
+                                                 ctypes.c_int64, _f64p, _f32p]
         lib.umi_oracle_detrend_batch_ex.restype = ctypes.c_int
         lib.umi_oracle_detrend_batch_ex.argtypes = [_f32p, _f64p, _i64p, ctypes.c_int64, _i32p,
-                                                    _f64p, _f64p, ctypes.c_int, ctypes.c_int,
-                                                    _f64p, _f32p, ctypes.c_int]
+                                                    _f64p, _f64p, _f64p, ctypes.c_int,
+                                                    ctypes.c_int, _f64p, _f32p, ctypes.c_int]
         lib.umi_oracle_normalise.restype = None
         lib.umi_oracle_normalise.argtypes = [_f32p, _f64p, ctypes.c_int64, _f64p]
         lib.umi_oracle_detrend_batch.restype = ctypes.c_int
@@ -176,8 +176,9 @@ def segments(flux, time, W):
     return lo, hi
 
 
-def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
-    """Whole curve: returns (trend float64, median float32)."""
+def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms", window_days=0.0):
+    """Whole curve: returns (trend float64, median float32).  ``window_days``
+    > 0 selects time windows of that length (W still bounds them)."""
     flux = _f32(flux)
     time = _f64(time)
     if time is not None and time.size != flux.size:
@@ -187,13 +188,15 @@ def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
     med = np.empty(n, np.float32)
     rc = _load().umi_oracle_detrend_ex(_ptr(flux, _f32p), _ptr(time, _f64p), n, int(W),
                                        float(alpha), float(c), int(iters), _scale(scale),
-                                       _ptr(trend, _f64p), _ptr(med, _f32p))
+                                       float(window_days), _ptr(trend, _f64p),
+                                       _ptr(med, _f32p))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med
 
 
-def detrend_at(flux, time, W, idx, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
+def detrend_at(flux, time, W, idx, alpha=2.0, c=5.0, iters=5, scale="upper_rms",
+               window_days=0.0):
     """Estimates only at positions ``idx`` of one curve."""
     flux = _f32(flux)
     time = _f64(time)
@@ -202,17 +205,18 @@ def detrend_at(flux, time, W, idx, alpha=2.0, c=5.0, iters=5, scale="upper_rms")
     med = np.empty(idx.size, np.float32)
     rc = _load().umi_oracle_detrend_at_ex(_ptr(flux, _f32p), _ptr(time, _f64p), flux.size,
                                           int(W), float(alpha), float(c), int(iters),
-                                          _scale(scale), _ptr(idx, _i64p), idx.size,
-                                          _ptr(trend, _f64p), _ptr(med, _f32p))
+                                          _scale(scale), float(window_days), _ptr(idx, _i64p),
+                                          idx.size, _ptr(trend, _f64p), _ptr(med, _f32p))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med
 
 
 def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, n_threads=None,
-                  scale="upper_rms"):
+                  scale="upper_rms", window_days=None):
     """Packed ragged batch; curves spread over ``n_threads`` host threads.
-    ``W``, ``alpha`` and ``c`` are scalars or one value per curve."""
+    ``W``, ``alpha``, ``c`` and ``window_days`` (time windows where > 0) are
+    scalars or one value per curve."""
     flux = _f32(flux)
     time = _f64(time)
     lengths = np.ascontiguousarray(lengths, dtype=np.int64)
@@ -225,11 +229,16 @@ def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, n_threads=N
     med = np.empty(flux.size, np.float32)
     al = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha, np.float64), lengths.shape))
     ca = np.ascontiguousarray(np.broadcast_to(np.asarray(c, np.float64), lengths.shape))
+    wd = None
+    if window_days is not None:
+        wd = np.ascontiguousarray(np.broadcast_to(np.asarray(window_days, np.float64),
+                                                  lengths.shape))
     rc = _load().umi_oracle_detrend_batch_ex(_ptr(flux, _f32p), _ptr(time, _f64p),
                                              _ptr(lengths, _i64p), lengths.size,
                                              _ptr(Wa, _i32p), _ptr(al, _f64p), _ptr(ca, _f64p),
-                                             int(iters), _scale(scale), _ptr(trend, _f64p),
-                                             _ptr(med, _f32p), int(n_threads))
+                                             _ptr(wd, _f64p), int(iters), _scale(scale),
+                                             _ptr(trend, _f64p), _ptr(med, _f32p),
+                                             int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return trend, med

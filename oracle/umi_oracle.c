@@ -46,7 +46,12 @@
  *   R16 per-curve alpha and c (the use-case settings of Table 4) change
  *      nothing else: each curve is estimated with its own pair;
  *   R17 the normalisation stage (a pipeline stage of Table 3) divides the flux
- *      by the trend: detrended = flux / trend, NaN wherever the trend is NaN.
+ *      by the trend: detrended = flux / trend, NaN wherever the trend is NaN;
+ *   R19 time windows (the window_length in days of Section 4.2, for irregular
+ *      cadence): with a window length L, sample i's window keeps only the
+ *      valid samples j of its index window (R1) with |t_j - t_i| <= L/2, the
+ *      difference taken in float64; W then bounds the samples a window may
+ *      hold.
  *
  * Precision: inputs are float32 (flux) and float64 (time); every arithmetic
  * step is float64; the median is returned as the exact float32 element.
@@ -278,8 +283,8 @@ int64_t umi_oracle_segments(const float* flux, const double* time, int64_t n,
 static void estimate_at(const float* flux, const double* time, int64_t i, int W,
                         const int64_t* seg_lo, const int64_t* seg_hi,
                         double alpha, double c, int iters, int scale_mode,
-                        float* buf, uint32_t* keys, double* trend_out,
-                        float* median_out)
+                        double window_days, float* buf, uint32_t* keys,
+                        double* trend_out, float* median_out)
 {
     if (seg_lo[i] < 0) {
         *trend_out = NAN;
@@ -291,8 +296,12 @@ static void estimate_at(const float* flux, const double* time, int64_t i, int W,
     if (a < seg_lo[i]) a = seg_lo[i];
     if (b > seg_hi[i]) b = seg_hi[i];
     int n = 0;
-    for (int64_t q = a; q <= b; ++q)
-        if (sample_valid(flux, time, q)) buf[n++] = flux[q];
+    for (int64_t q = a; q <= b; ++q) {
+        if (!sample_valid(flux, time, q)) continue;
+        /* reading R19: a time window keeps samples within half its length */
+        if (window_days > 0.0 && !(fabs(time[q] - time[i]) <= 0.5 * window_days)) continue;
+        buf[n++] = flux[q];
+    }
     float med;
     *trend_out = window_estimate(buf, n, alpha, c, iters, scale_mode, keys, &med, NULL);
     if (median_out) *median_out = med;
@@ -309,11 +318,16 @@ static int params_ok(int64_t n, int W, double alpha, double c, int iters)
 
 /* Full curve: trend (FP64) and median (exact float32) at every sample.
  * Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+/* window_days > 0 selects time windows (reading R19; needs `time`), else
+ * index windows. */
 int umi_oracle_detrend_ex(const float* flux, const double* time, int64_t n,
                           int W, double alpha, double c, int iters,
-                          int scale_mode, double* trend, float* median)
+                          int scale_mode, double window_days, double* trend,
+                          float* median)
 {
     if (!params_ok(n, W, alpha, c, iters)) return -1;
+    if (window_days > 0.0 && !time) return -1;
+    if (!(window_days <= 0.0 || isfinite(window_days))) return -1;
     if (scale_mode != ORACLE_SCALE_UPPER_RMS && scale_mode != ORACLE_SCALE_MAD) return -1;
     if (n == 0) return 0;
     int64_t* lo = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
@@ -327,8 +341,8 @@ int umi_oracle_detrend_ex(const float* flux, const double* time, int64_t n,
     }
     umi_oracle_segments(flux, time, n, W, lo, hi);
     for (int64_t i = 0; i < n; ++i)
-        estimate_at(flux, time, i, W, lo, hi, alpha, c, iters, scale_mode, buf,
-                    keys, &trend[i], median ? &median[i] : NULL);
+        estimate_at(flux, time, i, W, lo, hi, alpha, c, iters, scale_mode,
+                    window_days, buf, keys, &trend[i], median ? &median[i] : NULL);
 done:
     free(lo);
     free(hi);
@@ -342,17 +356,19 @@ int umi_oracle_detrend(const float* flux, const double* time, int64_t n, int W,
                        float* median)
 {
     return umi_oracle_detrend_ex(flux, time, n, W, alpha, c, iters,
-                                 ORACLE_SCALE_UPPER_RMS, trend, median);
+                                 ORACLE_SCALE_UPPER_RMS, 0.0, trend, median);
 }
 
 /* Only at the listed positions of one curve (segments still come from the
  * whole curve): used to check sampled outputs of large workloads. */
 int umi_oracle_detrend_at_ex(const float* flux, const double* time, int64_t n,
                              int W, double alpha, double c, int iters,
-                             int scale_mode, const int64_t* idx, int64_t n_idx,
-                             double* trend, float* median)
+                             int scale_mode, double window_days,
+                             const int64_t* idx, int64_t n_idx, double* trend,
+                             float* median)
 {
     if (!params_ok(n, W, alpha, c, iters) || n_idx < 0) return -1;
+    if (window_days > 0.0 && !time) return -1;
     if (scale_mode != ORACLE_SCALE_UPPER_RMS && scale_mode != ORACLE_SCALE_MAD) return -1;
     for (int64_t k = 0; k < n_idx; ++k)
         if (idx[k] < 0 || idx[k] >= n) return -1;
@@ -369,7 +385,7 @@ int umi_oracle_detrend_at_ex(const float* flux, const double* time, int64_t n,
     umi_oracle_segments(flux, time, n, W, lo, hi);
     for (int64_t k = 0; k < n_idx; ++k)
         estimate_at(flux, time, idx[k], W, lo, hi, alpha, c, iters, scale_mode,
-                    buf, keys, &trend[k], median ? &median[k] : NULL);
+                    window_days, buf, keys, &trend[k], median ? &median[k] : NULL);
 done:
     free(lo);
     free(hi);
@@ -384,8 +400,8 @@ int umi_oracle_detrend_at(const float* flux, const double* time, int64_t n,
                           float* median)
 {
     return umi_oracle_detrend_at_ex(flux, time, n, W, alpha, c, iters,
-                                    ORACLE_SCALE_UPPER_RMS, idx, n_idx, trend,
-                                    median);
+                                    ORACLE_SCALE_UPPER_RMS, 0.0, idx, n_idx,
+                                    trend, median);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -402,6 +418,7 @@ typedef struct {
     int64_t n_curves;
     const double* alpha; /* per curve (reading R16) */
     const double* c;
+    const double* window_days; /* per curve, or NULL (reading R19) */
     int iters;
     int scale_mode;
     double* trend;
@@ -423,7 +440,8 @@ static void* batch_worker(void* arg)
         int rc = umi_oracle_detrend_ex(
             job->flux + off, job->time ? job->time + off : NULL, job->lengths[b],
             job->W[b], job->alpha[b], job->c[b], job->iters, job->scale_mode,
-            job->trend + off, job->median ? job->median + off : NULL);
+            job->window_days ? job->window_days[b] : 0.0, job->trend + off,
+            job->median ? job->median + off : NULL);
         if (rc != 0) {
             pthread_mutex_lock(&job->mu);
             job->rc = rc;
@@ -437,8 +455,9 @@ static void* batch_worker(void* arg)
 int umi_oracle_detrend_batch_ex(const float* flux, const double* time,
                                 const int64_t* lengths, int64_t n_curves,
                                 const int* W, const double* alpha,
-                                const double* c, int iters, int scale_mode,
-                                double* trend, float* median, int n_threads)
+                                const double* c, const double* window_days,
+                                int iters, int scale_mode, double* trend,
+                                float* median, int n_threads)
 {
     if (n_curves < 0) return -1;
     if (n_curves == 0) return 0;
@@ -453,8 +472,10 @@ int umi_oracle_detrend_batch_ex(const float* flux, const double* time,
         offsets[b] = acc;
         acc += lengths[b];
     }
-    batch_job job = {flux, time, lengths, offsets, W, n_curves, alpha, c, iters,
-                     scale_mode, trend, median, 0, PTHREAD_MUTEX_INITIALIZER, 0};
+    batch_job job = {flux,  time,        lengths, offsets,
+                     W,     n_curves,    alpha,   c,
+                     window_days, iters, scale_mode, trend,
+                     median, 0,          PTHREAD_MUTEX_INITIALIZER, 0};
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
     pthread_t tids[256];
@@ -485,8 +506,8 @@ int umi_oracle_detrend_batch(const float* flux, const double* time,
             cc[b] = c;
         }
         rc = umi_oracle_detrend_batch_ex(flux, time, lengths, n_curves, W, a, cc,
-                                         iters, ORACLE_SCALE_UPPER_RMS, trend,
-                                         median, n_threads);
+                                         NULL, iters, ORACLE_SCALE_UPPER_RMS,
+                                         trend, median, n_threads);
     }
     free(a);
     free(cc);

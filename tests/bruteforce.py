@@ -108,7 +108,7 @@ def estimate(xs, alpha, c, iters, scale="upper_rms"):
     return mu, m
 
 
-def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
+def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms", window_days=0.0):
     flux = [f32(float(v)) for v in flux]
     time = None if time is None else [float(v) for v in time]
     n = len(flux)
@@ -121,6 +121,7 @@ def detrend(flux, time, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms"):
             continue
         lo, hi = seg[i]
         xs = [flux[j] for j in range(n)
-              if lo <= j <= hi and i - h <= j <= i + h and valid(flux, time, j)]
+              if lo <= j <= hi and i - h <= j <= i + h and valid(flux, time, j)
+              and (window_days <= 0 or 2 * abs(time[j] - time[i]) <= window_days)]
         trend[i], med[i] = estimate(xs, alpha, c, iters, scale)
     return trend, med

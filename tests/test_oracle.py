@@ -274,6 +274,71 @@ def test_normalise_definition(oracle_lib):
 
 
 # --------------------------------------------------------------------------
+# Time windows (window_length in days, Section 4.2; reading R19)
+
+
+def _irregular_cases():
+    rng = np.random.default_rng(41)
+    cases = []
+    for trial in range(24):
+        n = int(rng.integers(1, 50))
+        t = np.cumsum(rng.exponential(2 / 1440, n))          # irregular cadence
+        if n > 8 and rng.random() < 0.5:
+            t[n // 2:] += rng.uniform(0.01, 0.2)              # a pause shorter than a break
+        f = (1 + rng.normal(0, 1e-3, n)).astype(np.float32)
+        f[rng.random(n) < 0.1] = np.nan
+        W = int(rng.choice([5, 9, 25, 61]))
+        L = float(rng.choice([4 / 1440, 10 / 1440, 30 / 1440, 0.5]))
+        cases.append((f, t, W, L))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_time_windows_match_bruteforce(oracle_lib, case):
+    f, t, W, L = _irregular_cases()[case]
+    for a, c, sc in [(2.0, 5.0, "upper_rms"), (10.0, 2.5, "mad")]:
+        tr, md = oracle_lib.detrend(f, t, W, a, c, 5, scale=sc, window_days=L)
+        btr, bmd = bf.detrend(f, t, W, a, c, 5, scale=sc, window_days=L)
+        btr = np.array(btr)
+        assert np.array_equal(np.isnan(tr), np.isnan(btr))
+        ok = ~np.isnan(btr)
+        assert np.array_equal(md[ok].view(np.uint32), np.array(bmd, np.float32)[ok].view(np.uint32))
+        np.testing.assert_allclose(tr[ok], btr[ok], rtol=1e-12, atol=1e-15)
+
+
+def test_time_windows_reduce_to_index_windows_at_regular_cadence(oracle_lib):
+    """A time window at least as long as the index window (h samples each
+    side) holds exactly the same samples: the results are bit-identical."""
+    rng = np.random.default_rng(13)
+    dt = 2 / 1440
+    f = (1 + rng.normal(0, 1e-3, 3000)).astype(np.float32)
+    f[1000:1200] = np.nan
+    t = np.arange(3000) * dt
+    for W in [25, 361]:
+        i_tr, i_md = oracle_lib.detrend(f, t, W)
+        t_tr, t_md = oracle_lib.detrend(f, t, W, window_days=(W - 1) * dt * 1.0000001)
+        assert np.array_equal(i_tr, t_tr, equal_nan=True)
+        assert np.array_equal(i_md.view(np.uint32), t_md.view(np.uint32))
+        # half as long a window is a genuinely different estimate
+        h_tr, _ = oracle_lib.detrend(f, t, W, window_days=(W - 1) * dt / 2)
+        assert not np.array_equal(i_tr, h_tr, equal_nan=True)
+
+
+def test_time_window_hand_case(oracle_lib):
+    # times 0, .01, .02, .2, .21 (days); a 0.05-day window: sample 0 sees
+    # {0, 1, 2} (offsets 0, .01, .02 <= .025), sample 3 sees {3, 4}
+    t = np.array([0.0, 0.01, 0.02, 0.2, 0.21])
+    f = np.array([1.0, 4.0, 2.0, 7.0, 3.0], np.float32)
+    _, md = oracle_lib.detrend(f, t, 9, window_days=0.05)
+    assert list(md) == [2.0, 2.0, 2.0, 3.0, 3.0]
+    # shorter than the cadence: every window is its own sample
+    tr, md = oracle_lib.detrend(f, t, 9, window_days=0.001)
+    assert np.array_equal(md, f) and np.array_equal(tr, f.astype(np.float64))
+    with pytest.raises(ValueError):
+        oracle_lib.detrend(f, None, 9, window_days=0.05)   # needs times
+
+
+# --------------------------------------------------------------------------
 # Whole-window estimate, Sections 2.1-2.3
 
 

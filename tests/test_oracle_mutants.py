@@ -33,12 +33,14 @@ MUTANTS = {
     "window one sample too wide": ("int64_t h = (W - 1) / 2;", "int64_t h = (W + 1) / 2;"),
     "gap measured from segment start": ("(time[q] - time[last]) > ORACLE_GAP_DAYS", "(time[q] - time[lo]) > ORACLE_GAP_DAYS"),
     "minimum segment W/2 instead of W/3": ("int64_t m_min = W / 3;", "int64_t m_min = W / 2;"),
-    "invalid samples kept in windows": ("if (sample_valid(flux, time, q)) buf[n++] = flux[q];", "buf[n++] = flux[q];"),
+    "invalid samples kept in windows": ("        if (!sample_valid(flux, time, q)) continue;\n        /* reading R19", "        if (0) continue;\n        /* reading R19"),
     "MAD: upper median of deviations": ("double s = dev[(n - 1) / 2];", "double s = dev[n / 2];"),
     "MAD: scaled to sigma": ("double s = dev[(n - 1) / 2];", "double s = 1.4826 * dev[(n - 1) / 2];"),
     "MAD: deviations not absolute": ("dev[i] = fabs((double)x[i] - m);", "dev[i] = (double)x[i] - m;"),
     "per-curve alpha ignored": ("job->W[b], job->alpha[b], job->c[b],", "job->W[b], job->alpha[0], job->c[b],"),
     "normalise inverted": ("(double)flux[j] / trend[j];", "trend[j] / (double)flux[j];"),
+    "time window uses the full length as half-width": ("fabs(time[q] - time[i]) <= 0.5 * window_days", "fabs(time[q] - time[i]) <= window_days"),
+    "time window ignored": ("if (window_days > 0.0 && !(fabs", "if (window_days > 1e300 && !(fabs"),
 }
 
 
