@@ -111,6 +111,18 @@ typedef struct {
                             of every curve (the normalisation stage Table 3
                             lists), laid out like trend; NaN where the trend
                             is NaN.  float32 division, correctly rounded. */
+    const double* window_days; /* [host] n_curves per-curve window lengths in
+                            days, or NULL.  A value > 0 makes that curve's
+                            windows time windows (the window_length of
+                            Section 4.2, for irregular cadence): sample i's
+                            window keeps the valid samples j of its W-sample
+                            index window with |t_j - t_i| <= window_days / 2
+                            (float64), so W must be at least the largest
+                            number of samples such a window can hold.  Needs
+                            `time`, non-decreasing over each curve's valid
+                            samples (otherwise results are unspecified).  0 =
+                            the index window; negative or non-finite values
+                            give UMI_ERR_INVALID_ARG. */
 } umi_options;
 
 /*

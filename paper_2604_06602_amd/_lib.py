@@ -46,7 +46,8 @@ class Launch(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_void_p), ("c", ctypes.c_void_p), ("scale", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("detrended", ctypes.c_void_p)]
+                ("reserved", ctypes.c_int32), ("detrended", ctypes.c_void_p),
+                ("window_days", ctypes.c_void_p)]
 
 
 _vp = ctypes.c_void_p
@@ -185,10 +186,11 @@ class LaunchOptions:
                       ev(self.main_start), ev(self.main_stop))
 
 
-def _options(n_curves, alpha, c, scale, detrended_ptr):
+def _options(n_curves, alpha, c, scale, detrended_ptr, window_days=None):
     """(umi_options or None, scalar alpha, scalar c, arrays to keep alive).
     ``alpha`` and ``c`` are scalars or one value per curve; ``scale`` is a key
-    of SCALES.  None means the plain call suffices."""
+    of SCALES; ``window_days`` is None, a scalar or one value per curve (time
+    windows where > 0).  None means the plain call suffices."""
     if scale not in SCALES:
         raise ValueError("scale must be one of %s" % sorted(SCALES))
     a_arr = c_arr = None
@@ -207,19 +209,25 @@ def _options(n_curves, alpha, c, scale, detrended_ptr):
         if c_arr.shape != (n_curves,):
             raise ValueError("per-curve c needs %d values" % n_curves)
         c0 = 5.0
-    if a_arr is None and c_arr is None and scale == "upper_rms" and detrended_ptr is None:
+    w_arr = None
+    if window_days is not None:
+        w_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(window_days, np.float64),
+                                                     (n_curves,)))
+    if (a_arr is None and c_arr is None and scale == "upper_rms" and detrended_ptr is None
+            and w_arr is None):
         return None, a0, c0, ()
     o = Options(None if a_arr is None else a_arr.ctypes.data,
-                None if c_arr is None else c_arr.ctypes.data, SCALES[scale], 0, detrended_ptr)
-    return o, a0, c0, (a_arr, c_arr)
+                None if c_arr is None else c_arr.ctypes.data, SCALES[scale], 0, detrended_ptr,
+                None if w_arr is None else w_arr.ctypes.data)
+    return o, a0, c0, (a_arr, c_arr, w_arr)
 
 
 def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=5.0, iters=5,
                        launch: LaunchOptions | None = None, stream=None, scale="upper_rms",
-                       detrended=None):
+                       detrended=None, window_days=None):
     """Raw batch call on preallocated device tensors (packed ragged layout).
     ``alpha``/``c`` may hold one value per curve; ``detrended`` receives
-    flux / trend."""
+    flux / trend; ``window_days`` (> 0) selects time windows."""
     torch = _torch()
     lengths = np.ascontiguousarray(lengths, dtype=np.int64)
     Wa = np.ascontiguousarray(np.broadcast_to(np.asarray(W, dtype=np.int32), lengths.shape))
@@ -229,7 +237,7 @@ def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=
     op = _dev_ptr(trend, torch.float32, "trend", n)
     mp = _dev_ptr(median, torch.float32, "median", n)
     dp = _dev_ptr(detrended, torch.float32, "detrended", n)
-    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
+    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp, window_days)
     lp = None
     if launch is not None:
         lp = ctypes.byref(launch.as_struct())
@@ -248,7 +256,7 @@ def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=
 
 def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, with_median=False,
                   launch: LaunchOptions | None = None, stream=None, scale="upper_rms",
-                  with_detrended=False):
+                  with_detrended=False, window_days=None):
     """Packed ragged batch: returns (trend, median or None) as device tensors,
     plus the detrended flux when ``with_detrended``."""
     torch = _torch()
@@ -256,19 +264,19 @@ def detrend_batch(flux, time, lengths, W, alpha=2.0, c=5.0, iters=5, with_median
     median = torch.empty_like(flux) if with_median else None
     det = torch.empty_like(flux) if with_detrended else None
     detrend_batch_into(flux, time, lengths, W, trend, median, alpha, c, iters, launch, stream,
-                       scale, det)
+                       scale, det, window_days)
     return (trend, median, det) if with_detrended else (trend, median)
 
 
 def detrend(flux, time=None, W=361, alpha=2.0, c=5.0, iters=5, with_median=False, stream=None,
-            scale="upper_rms", with_detrended=False):
+            scale="upper_rms", with_detrended=False, window_days=None):
     """One curve: returns (trend, median or None) as device tensors, plus the
     detrended flux when ``with_detrended``."""
     torch = _torch()
     n = flux.numel()
-    if scale != "upper_rms" or with_detrended:
+    if scale != "upper_rms" or with_detrended or window_days is not None:
         return detrend_batch(flux, time, [n], W, alpha, c, iters, with_median, None, stream,
-                             scale, with_detrended)
+                             scale, with_detrended, window_days)
     trend = torch.empty_like(flux)
     median = torch.empty_like(flux) if with_median else None
     st = lib.umi_detrend(_dev_ptr(flux, torch.float32, "flux", n),
@@ -303,14 +311,14 @@ def _span_ptr(t, dtype, name, span):
 
 def detrend_gather_into(flux, time, offsets, lengths, W, trend, median=None, alpha=2.0, c=5.0,
                         iters=5, launch: LaunchOptions | None = None, stream=None,
-                        scale="upper_rms", detrended=None):
+                        scale="upper_rms", detrended=None, window_days=None):
     """Curves at explicit sample offsets of the device arrays (no packing)."""
     torch = _torch()
     offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
     span = int((offsets + np.maximum(lengths, 0)).max()) if lengths.size else 0
     lp = ctypes.byref(launch.as_struct()) if launch is not None else None
     dp = _span_ptr(detrended, torch.float32, "detrended", span)
-    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
+    opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp, window_days)
     args = (_span_ptr(flux, torch.float32, "flux", span),
             _span_ptr(time, torch.float64, "time", span),
             offsets.ctypes.data_as(_i64p), lengths.ctypes.data_as(_i64p),
@@ -350,7 +358,7 @@ class Plan:
         self.max_W = int(max_W)
 
     def run(self, offsets, lengths, W, alpha=2.0, c=5.0, iters=5, scale="upper_rms",
-            detrended=None):
+            detrended=None, window_days=None):
         """Stage and replay one batch; ``alpha``/``c`` may hold one value per
         curve; ``detrended`` (capacity samples) receives flux / trend."""
         if self._h is None:
@@ -358,7 +366,7 @@ class Plan:
         torch = _torch()
         offsets, lengths, Wa = _host_arrays(offsets, lengths, W)
         dp = _span_ptr(detrended, torch.float32, "detrended", self.capacity)
-        opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp)
+        opts, a0, c0, keep = _options(lengths.size, alpha, c, scale, dp, window_days)
         if opts is None:
             st = lib.umi_plan_run(self._h, offsets.ctypes.data_as(_i64p),
                                   lengths.ctypes.data_as(_i64p), Wa.ctypes.data_as(_i32p),

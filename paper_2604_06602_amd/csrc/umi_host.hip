@@ -120,9 +120,10 @@ umi_status check_params(float alpha, float c, int32_t iters)
 
 // The extra options of the _ex calls (NULL = the plain method with the
 // call's alpha and c for every curve).
-umi_status check_options(const umi_options* o, int64_t n_curves, umi_options* out)
+umi_status check_options(const umi_options* o, int64_t n_curves, const double* time,
+                         umi_options* out)
 {
-    *out = umi_options{nullptr, nullptr, UMI_SCALE_UPPER_RMS, 0, nullptr};
+    *out = umi_options{nullptr, nullptr, UMI_SCALE_UPPER_RMS, 0, nullptr, nullptr};
     if (!o) return UMI_OK;
     *out = *o;
     if (o->reserved != 0) return fail(UMI_ERR_INVALID_ARG, "umi_options.reserved must be 0");
@@ -133,6 +134,13 @@ umi_status check_options(const umi_options* o, int64_t n_curves, umi_options* ou
             return fail(UMI_ERR_INVALID_ARG, "per-curve alpha must be finite and > 0");
         if (o->c && !finite_pos(o->c[b]))
             return fail(UMI_ERR_INVALID_ARG, "per-curve c must be finite and > 0");
+        if (o->window_days) {
+            const double L = o->window_days[b];
+            if (!std::isfinite(L) || L < 0.0)
+                return fail(UMI_ERR_INVALID_ARG, "window_days must be finite and >= 0");
+            if (L > 0.0 && !time)
+                return fail(UMI_ERR_INVALID_ARG, "time windows need the time array");
+        }
     }
     return UMI_OK;
 }
@@ -222,6 +230,7 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
         d.tile_base = (int32_t)out->ntiles;
         d.alpha = o.alpha ? o.alpha[b] : alpha;
         d.c = o.c ? o.c[b] : c;
+        d.window_days = o.window_days ? o.window_days[b] : 0.0;
         out->curve_tiles[i] = nt;
         out->ntiles += nt;
     }
@@ -239,7 +248,8 @@ size_t block_bytes(int64_t ncurves)
     return sizeof(BatchHeader) + (size_t)ncurves * sizeof(CurveDesc);
 }
 
-void write_block(uint8_t* dst, const Packed& p, int32_t iters, const umi_options& o)
+void write_block(uint8_t* dst, const Packed& p, int32_t iters, const umi_options& o,
+                 const double* time)
 {
     BatchHeader h = {};
     h.n_curves = (int32_t)p.curves.size();
@@ -247,6 +257,7 @@ void write_block(uint8_t* dst, const Packed& p, int32_t iters, const umi_options
     h.iters = iters;
     h.scale = o.scale;
     h.detrended = o.detrended;
+    h.time = time;
     std::memcpy(dst, &h, sizeof h);
     if (!p.curves.empty())
         std::memcpy(dst + sizeof h, p.curves.data(), p.curves.size() * sizeof(CurveDesc));
@@ -445,7 +456,7 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     if ((st = check_launch(launch, &opt)) != UMI_OK) return st;
     if ((st = check_params(alpha, c, iters)) != UMI_OK) return st;
     umi_options o;
-    if ((st = check_options(options, n_curves, &o)) != UMI_OK) return st;
+    if ((st = check_options(options, n_curves, time, &o)) != UMI_OK) return st;
     int64_t span, total;
     if ((st = check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK) return st;
     if (total == 0) return UMI_OK;
@@ -467,7 +478,7 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
             return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
-    write_block(ws->hblock, p, iters, o);
+    write_block(ws->hblock, p, iters, o, time);
     if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return fail_hip(e, "curve table copy");
@@ -662,7 +673,7 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
         return umi::fail(UMI_ERR_INVALID_ARG, "offsets, lengths and W must not be NULL");
     if ((st = umi::check_params(alpha, c, iters)) != UMI_OK) return st;
     umi_options o;
-    if ((st = umi::check_options(options, n_curves, &o)) != UMI_OK) return st;
+    if ((st = umi::check_options(options, n_curves, p->time, &o)) != UMI_OK) return st;
     int64_t span = 0, total = 0;
     if (n_curves > 0 &&
         (st = umi::check_curves(offsets, lengths, n_curves, W, &span, &total)) != UMI_OK)
@@ -687,7 +698,7 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
             return umi::fail_hip(e, "hipEventSynchronize");
         s.pending = false;
     }
-    umi::write_block(s.host, pk, iters, o);
+    umi::write_block(s.host, pk, iters, o, p->time);
     if (!s.exec) {
         // capture once per slot: copy of the staged block, pre-pass over
         // max_curves (blocks beyond the batch exit), persistent estimate
@@ -793,7 +804,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.4.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.5.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

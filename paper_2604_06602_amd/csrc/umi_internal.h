@@ -27,7 +27,7 @@ struct BatchHeader {
     int32_t iters;      // Phase 3 iterations
     int32_t scale;      // umi_scale: Phase 2 estimator
     float* detrended;   // flux / trend output (curve offsets as for trend), or null
-    int64_t pad;
+    const double* time; // the batch's times (read by the time-window scans), or null
 };
 static_assert(sizeof(BatchHeader) == 32, "BatchHeader layout");
 
@@ -40,8 +40,9 @@ struct CurveDesc {
     int32_t tile_base;  // index of this curve's first tile in the tile list
     float alpha;        // asymmetry factor (Eq. 2) of this curve
     float c;            // bisquare tuning constant of this curve
+    double window_days; // > 0: time window of this length (W still bounds it)
 };
-static_assert(sizeof(CurveDesc) == 32, "CurveDesc layout");
+static_assert(sizeof(CurveDesc) == 40, "CurveDesc layout");
 
 // Segment record written by the pre-pass at segtab[curve.off + segment id]:
 //   x = first valid index, y = last valid index (curve-local),

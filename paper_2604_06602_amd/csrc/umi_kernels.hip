@@ -539,6 +539,7 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
                                              const int32_t* __restrict__ segid,
                                              const int4* __restrict__ segtab, float alpha,
                                              float c, int iters, int scale,
+                                             const double* __restrict__ time,
                                              float* __restrict__ trend,
                                              float* __restrict__ median,
                                              float* __restrict__ detrended)
@@ -558,10 +559,21 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
             if (sidp >= 0) {
                 const int4 seg = segtab[cd.off + sidp];
                 if (seg.w - seg.z >= m_min) {
-                    const int a = max(p - h, seg.x) - s0;
-                    const int b = min(p + h, seg.y) - s0 + 1;
-                    ca[r] = rank1(sm.vbits, sm.vpre, (uint32_t)a);
-                    n[r] = rank1(sm.vbits, sm.vpre, (uint32_t)b) - ca[r];  // >= 1: p is valid
+                    int a = max(p - h, seg.x);
+                    int b = min(p + h, seg.y);
+                    if (cd.window_days > 0.0) {
+                        // time window: only the samples within half its length
+                        // of p count.  Times are non-decreasing, so they form a
+                        // run that two scans in from the index window's ends find
+                        // (invalid samples inside it are skipped by the ranks).
+                        const double* tc = time + cd.off;
+                        const double ti = tc[p];
+                        const double half = 0.5 * cd.window_days;
+                        while (a < p && !(__builtin_fabs(tc[a] - ti) <= half)) ++a;
+                        while (b > p && !(__builtin_fabs(tc[b] - ti) <= half)) --b;
+                    }
+                    ca[r] = rank1(sm.vbits, sm.vpre, (uint32_t)(a - s0));
+                    n[r] = rank1(sm.vbits, sm.vpre, (uint32_t)(b - s0 + 1)) - ca[r];  // >= 1: p is valid
                     live[r] = true;
                 }
             }
@@ -675,6 +687,7 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const int iters = hdr->iters;
     const int scale = hdr->scale;
     float* const detrended = hdr->detrended;
+    const double* const time = hdr->time;
     // tile range [tile_first, tile_end): a count < 0 means "all tiles of the batch"
     const int tile_end = tile_count < 0 ? hdr->n_tiles : tile_first + tile_count;
 
@@ -788,13 +801,13 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         const int R = (t1 - t0 + kMainThreads - 1) / kMainThreads;  // tile <= kMaxTile -> R <= 3
         if (R == 3)
             tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            trend, median, detrended);
+                            time, trend, median, detrended);
         else if (R == 2)
             tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            trend, median, detrended);
+                            time, trend, median, detrended);
         else
             tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            trend, median, detrended);
+                            time, trend, median, detrended);
         __syncthreads();
     }
 }

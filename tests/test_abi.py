@@ -148,15 +148,17 @@ def test_options_validation_without_device(lib):
     L = np.asarray([10, 20], np.int64)
     w = np.asarray([5, 7], np.int32)
 
-    def call(alpha=None, c=None, scale=0, reserved=0, offsets=None):
+    def call(alpha=None, c=None, scale=0, reserved=0, offsets=None, window_days=None,
+             time=None):
         a = None if alpha is None else np.asarray(alpha, np.float32)
         cc = None if c is None else np.asarray(c, np.float32)
+        wd = None if window_days is None else np.asarray(window_days, np.float64)
         o = lib.Options(None if a is None else a.ctypes.data, None if cc is None else cc.ctypes.data,
-                        scale, reserved, None)
+                        scale, reserved, None, None if wd is None else wd.ctypes.data)
         offs = None if offsets is None else np.asarray(offsets, np.int64)
         lib.debug_inject_error(0)
         return lib.lib.umi_detrend_gather_ex(
-            ctypes.c_void_p(1), None, None if offs is None else offs.ctypes.data_as(i64),
+            ctypes.c_void_p(1), time, None if offs is None else offs.ctypes.data_as(i64),
             L.ctypes.data_as(i64), L.size, w.ctypes.data_as(i32), 2.0, 5.0, 5,
             ctypes.c_void_p(1), None, ctypes.byref(o), None, None)
     assert call(alpha=[2.0, 0.0]) == 1
@@ -167,6 +169,9 @@ def test_options_validation_without_device(lib):
     assert call(scale=-1) == 1
     assert call(reserved=1) == 1
     assert call(alpha=[2.0, 3.0], offsets=[0, 5]) == 1    # overlapping explicit offsets
+    assert call(window_days=[0.5, -1.0], time=ctypes.c_void_p(8)) == 1
+    assert call(window_days=[0.5, float("nan")], time=ctypes.c_void_p(8)) == 1
+    assert call(window_days=[0.5, 0.0]) == 1              # time windows need times
     with pytest.raises(ValueError):
         lib._options(2, [2.0], 5.0, "upper_rms", None)    # wrong per-curve count
     with pytest.raises(ValueError):

@@ -153,3 +153,44 @@ def test_plan_run_ex_equals_gather_ex(torch, umi):
                 assert (p_tr[b.flux.size:] == -1.0).all() and (p_det[b.flux.size:] == -1.0).all()
     finally:
         plan.destroy()
+
+
+def _irregular_batch(n_curves=8, seed=77):
+    """Irregular cadence (exponential steps, mean 2 min), pauses shorter than
+    a segment break, isolated NaNs: non-decreasing times throughout."""
+    rng = np.random.default_rng(seed)
+    curves = []
+    for i in range(n_curves):
+        n = int(rng.integers(1500, 4000))
+        t = np.cumsum(rng.exponential(2 / 1440, n))
+        for _ in range(2):
+            k = int(rng.integers(1, n))
+            t[k:] += rng.uniform(0.01, 0.3)
+        f = 1 + 1e-3 * rng.normal(size=n) + 2e-3 * np.sin(2 * np.pi * t / 1.7)
+        f[rng.random(n) < 0.03] = np.nan
+        curves.append((f.astype(np.float32), t, 1441))
+    return synth.lightcurves.pack(curves)
+
+
+def test_time_windows_irregular_cadence(torch, umi, oracle_lib):
+    b = _irregular_batch()
+    for L, sc in [(0.5, "upper_rms"), (0.25, "mad"), (1.0, "upper_rms")]:
+        g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, window_days=L, scale=sc)
+        o_tr, o_md = oracle_lib.detrend_batch(b.flux, b.time, b.lengths, b.W, window_days=L,
+                                              scale=sc)
+        assert_parity(g_tr, g_md, o_tr, o_md, what="time windows L=%g %s" % (L, sc))
+    # a mixed batch: some curves with time windows, some with index windows
+    wd = np.array([0.5 if i % 2 else 0.0 for i in range(b.n_curves)])
+    g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, window_days=wd)
+    o_tr, o_md = oracle_lib.detrend_batch(b.flux, b.time, b.lengths, b.W, window_days=wd)
+    assert_parity(g_tr, g_md, o_tr, o_md, what="mixed time/index windows")
+
+
+def test_time_windows_equal_index_windows_at_regular_cadence(torch, umi):
+    b = _mixed_batch(8)
+    dt = 2 / 1440
+    ref, ref_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W)
+    wd = (np.asarray(b.W, np.float64) - 1) * dt * 1.0000001
+    tw, tw_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, window_days=wd)
+    assert np.array_equal(ref.view(np.uint32), tw.view(np.uint32))
+    assert np.array_equal(ref_md.view(np.uint32), tw_md.view(np.uint32))
