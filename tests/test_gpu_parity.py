@@ -136,6 +136,33 @@ def test_config1_full_size_sampled(torch, umi, oracle_lib):
     assert np.isfinite(g_tr).sum() == 1000 * (18000 - 720)
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_config_full_size_sampled(torch, umi, oracle_lib, cfg):
+    """Workloads 2 (2,000 Kepler-like curves, W = 25) and 3 (10,000 mixed
+    curves, W in {25, 121, 361, 721}, NaN gaps) whole, in the benchmark's
+    launch configuration (its tuning table); sampled outputs of sampled curves
+    against the oracle, and the NaN pattern of every sampled curve against the
+    oracle's segmentation."""
+    from paper_2604_06602_amd import autotune
+    b = synth.config_batch(cfg)
+    autotune.apply()
+    try:
+        g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W)
+    finally:
+        umi.set_tuning(None)
+    rng = np.random.default_rng(100 + cfg)
+    off = b.offsets
+    for ci in rng.choice(b.n_curves, 16, replace=False):
+        f, t, W = b.curve(ci)
+        idx = np.unique(np.concatenate([[0, 1, f.size - 2, f.size - 1], rng.integers(0, f.size, 120)]))
+        idx = idx[(idx >= 0) & (idx < f.size)]
+        o_tr, o_md = oracle_lib.detrend_at(f, t, W, idx)
+        sl = off[ci] + idx
+        assert_parity(g_tr[sl], g_md[sl], o_tr, o_md, what="config%d curve %d" % (cfg, ci))
+        lo, _ = oracle_lib.segments(f, t, W)
+        assert np.array_equal(np.isnan(g_tr[off[ci]:off[ci] + f.size]), lo < 0)
+
+
 def edge_case_batch():
     """Empty, tiny, all-invalid, dead-segment, invalid-time, tied, signed-zero,
     constant, negative, large-offset, W=1, sparse and largest-W curves."""
