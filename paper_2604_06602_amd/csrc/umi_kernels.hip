@@ -437,7 +437,7 @@ __device__ __forceinline__ void bisquare_multi(const float* __restrict__ x, int 
 #pragma unroll
             for (int r = 0; r <= j; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
         }
-#pragma unroll 4
+#pragma unroll 8
         for (int j = R - 1; j < n; ++j) {  // every window
             const float xj = x[j];
 #pragma unroll
@@ -532,13 +532,55 @@ __device__ __forceinline__ float window_mad(const MainSmem& sm, int levels, uint
     return mad;
 }
 
+// Phase 1 for a full window of W <= kSmallW samples whose totalOrder keys sit
+// at kp[0 .. W): a bitonic network over 32 registers (padded with the largest
+// key) sorts them, the element of rank (W-1)/2 is the median, and the points
+// strictly above it are counted on the unsorted keys.  Same results as the
+// tile-sort path, without the tile sort and wavelet matrix.
+constexpr int kSmallW = 31;
+
+__device__ __forceinline__ void small_window_median(const uint32_t* __restrict__ kp, int W,
+                                                    float& m, uint32_t& nplus)
+{
+    uint32_t k[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) k[i] = i < W ? kp[i] : 0xffffffffu;
+#pragma unroll
+    for (int kk = 2; kk <= 32; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const uint32_t a = k[i], b = k[l];
+                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    k[i] = (i & kk) == 0 ? lo : hi;
+                    k[l] = (i & kk) == 0 ? hi : lo;
+                }
+            }
+        }
+    }
+    const int q = (W - 1) >> 1;  // <= 15, the same for the whole tile
+    uint32_t mk = k[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) mk = q == i ? k[i] : mk;
+    m = key_value(mk);
+    // strictly above, numerically: -0 and +0 are equal
+    const uint32_t T = m == 0.0f ? order_key(0.0f) : mk;
+    uint32_t cnt = 0;
+    for (int j = 0; j < W; ++j) cnt += kp[j] > T ? 1u : 0u;
+    nplus = cnt;
+}
+
 // The windows of one tile: each lane takes R consecutive output positions.
 template <int R>
 __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int nv,
                                              const CurveDesc& cd, int h, int s0, int t0, int t1,
                                              const int32_t* __restrict__ segid,
                                              const int4* __restrict__ segtab, float alpha,
-                                             float c, int iters, int scale,
+                                             float c, int iters, int scale, bool simple,
+                                             const float* pm, const uint32_t* pn,
                                              const double* __restrict__ time,
                                              float* __restrict__ trend,
                                              float* __restrict__ median,
@@ -595,7 +637,10 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         m[r] = 0.0f;
         sc[r] = 0.0f;
         nplus[r] = 0;
-        if (live[r]) {
+        if (live[r] && simple) {
+            m[r] = pm[r];  // from the small-window networks
+            nplus[r] = pn[r];
+        } else if (live[r]) {
             const uint32_t cb = ca[r] + n[r];
             const uint32_t rk = wavelet_kth(sm, levels, ca[r], cb, (n[r] - 1) >> 1);
             m[r] = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
@@ -713,14 +758,23 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         const int32_t* sg = segid + cd.off + s0;
 
         // --- staged validity bit vector (valid = finite flux and time) ---
+        // A tile is "simple" when every one of its windows is full: a small
+        // W, no curve end within reach, and the whole span valid and in one
+        // segment.  Its medians then come from per-window networks.
+        const int sg0 = sg[0];
+        bool same = true;
         const int nwv = (N >> 6) + 1;
         for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
             const int i = i0 + lane;
-            const bool ok = (i < N) && (sg[i] >= 0);
+            const int sgi = i < N ? sg[i] : sg0;
+            const bool ok = (i < N) && (sgi >= 0);
+            same = same && sgi == sg0;
             const uint64_t bal = __ballot(ok);
             if (lane == 0) sm.vbits[i0 >> 6] = bal;
         }
-        __syncthreads();
+        const bool simple = __syncthreads_and(same) && sg0 >= 0 && cd.W <= kSmallW &&
+                            scale != UMI_SCALE_MAD && cd.window_days == 0.0 && t0 >= h &&
+                            t1 + h <= cd.len;
         word_prefix(sm.vbits, sm.vpre, nwv, reinterpret_cast<uint32_t*>(&sm.nvalid));
         __syncthreads();
         const int nv = sm.nvalid;
@@ -729,6 +783,16 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         int levels = 6;
         while ((1 << levels) < npad) ++levels;
 
+        if (simple) {
+            // every staged sample is valid: values and keys in index order
+            uint32_t* keys = reinterpret_cast<uint32_t*>(sm.seq);
+            for (int i = tid; i < N; i += kMainThreads) {
+                const float x = f[i];
+                sm.xv[i] = x;
+                keys[i] = order_key(x);
+            }
+            __syncthreads();
+        } else {
         // --- compaction: values in index order, (key, index) for the sort ---
         for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
             const int i = i0 + lane;
@@ -796,18 +860,32 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
             __syncthreads();
         }
+        }  // not simple
 
         // --- the tile's windows: R consecutive positions per lane ---
         const int R = (t1 - t0 + kMainThreads - 1) / kMainThreads;  // tile <= kMaxTile -> R <= 3
+        // Simple tiles: Phase 1 of this lane's windows from the networks, run
+        // here where few registers are live (every window is [p-h, p+h], all
+        // of it valid, so its keys start at staged index p - h - s0).
+        float pm[3] = {0.0f, 0.0f, 0.0f};
+        uint32_t pn[3] = {0u, 0u, 0u};
+        if (simple) {
+            const uint32_t* keys = reinterpret_cast<const uint32_t*>(sm.seq);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int p = t0 + tid * R + r;
+                if (r < R && p < t1) small_window_median(keys + (p - h - s0), cd.W, pm[r], pn[r]);
+            }
+        }
         if (R == 3)
             tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            time, trend, median, detrended);
+                            simple, pm, pn, time, trend, median, detrended);
         else if (R == 2)
             tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            time, trend, median, detrended);
+                            simple, pm, pn, time, trend, median, detrended);
         else
             tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
-                            time, trend, median, detrended);
+                            simple, pm, pn, time, trend, median, detrended);
         __syncthreads();
     }
 }
