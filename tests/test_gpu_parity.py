@@ -210,6 +210,34 @@ def test_edge_cases(torch, umi, oracle_lib):
                       scale=mag)
 
 
+def test_small_window_network_path(torch, umi, oracle_lib):
+    """Tiles whose windows are all full and W <= 31 take their medians from
+    per-window networks: every odd W up to 31 (and 33, just beyond), heavy
+    ties, signed zeros and constant runs, with and without invalid samples
+    (which send tiles back to the general path) -- median bit-exact, trend
+    within tolerance."""
+    rng = np.random.default_rng(21)
+    dt = 2 / 1440
+    curves = []
+    for W in list(range(1, 32, 2)) + [33]:
+        f = np.round(rng.normal(1, 1e-3, 4000), 4).astype(np.float32)   # ties
+        curves.append((f, np.arange(4000) * dt, W))
+        z = rng.choice(np.array([-0.0, 0.0, 0.0, 1e-3, -1e-3, 2e-3], np.float32), 3000)
+        curves.append((z, np.arange(3000) * dt, W))
+        g = rng.normal(1, 1e-3, 3500).astype(np.float32)
+        g[rng.random(3500) < 0.02] = np.nan
+        g[1000:1300] = 1.0
+        curves.append((g, np.arange(3500) * dt, W))
+    packed = synth.lightcurves.pack(curves)
+    mag = window_magnitude(packed.flux, packed.time, packed.lengths, packed.W, oracle_lib)
+    for a, c in [(2.0, 5.0), (10.0, 2.5)]:
+        g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths, packed.W,
+                               alpha=a, c=c)
+        o_tr, o_md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W,
+                                              alpha=a, c=c)
+        assert_parity(g_tr, g_md, o_tr, o_md, what="small W a=%g" % a, scale=mag)
+
+
 def test_no_time_array(torch, umi, oracle_lib):
     rng = np.random.default_rng(8)
     f = rng.normal(1, 1e-3, 7000).astype(np.float32)
