@@ -125,8 +125,26 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
 
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
+    constexpr int kChunk = kPrepThreads * kPrepItems;
 
-    for (int base = 0; base < cd.len; base += kPrepThreads * kPrepItems) {
+    // The next chunk's flux and times are loaded while the current one is
+    // scanned, so the loads' latency overlaps the block scans.
+    float fv[kPrepItems];
+    double tv[kPrepItems];
+    auto load_chunk = [&](int base, float* fo, double* to) {
+#pragma unroll
+        for (int q = 0; q < kPrepItems; ++q) {
+            const int e = base + (int)threadIdx.x * kPrepItems + q;
+            fo[q] = e < cd.len ? f[e] : __builtin_nanf("");
+            to[q] = (tm != nullptr && e < cd.len) ? tm[e] : 0.0;
+        }
+    };
+    load_chunk(0, fv, tv);
+
+    for (int base = 0; base < cd.len; base += kChunk) {
+        float nf[kPrepItems];
+        double nt[kPrepItems];
+        if (base + kChunk < cd.len) load_chunk(base + kChunk, nf, nt);
         const int e0 = base + (int)threadIdx.x * kPrepItems;
         uint32_t vmask = 0;  // bit q: item q is valid
         double t[kPrepItems];
@@ -135,20 +153,12 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
 #pragma unroll
         for (int q = 0; q < kPrepItems; ++q) {
             const int e = e0 + q;
-            bool ok = false;
-            double tv = 0.0;
-            if (e < cd.len) {
-                ok = isfinite(f[e]);
-                if (tm) {
-                    tv = tm[e];
-                    ok = ok && isfinite(tv);
-                }
-            }
+            const bool ok = e < cd.len && isfinite(fv[q]) && (tm == nullptr || isfinite(tv[q]));
             vmask |= (ok ? 1u : 0u) << q;
-            t[q] = tv;
+            t[q] = tv[q];
             if (ok) {
                 a_idx = e;
-                a_t = tv;
+                a_t = tv[q];
                 ++a_cnt;
             }
         }
@@ -240,6 +250,11 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
         }
         c_vc += tot_cnt;
         c_ns += tot_st;
+#pragma unroll
+        for (int q = 0; q < kPrepItems; ++q) {
+            fv[q] = nf[q];
+            tv[q] = nt[q];
+        }
         __syncthreads();  // sh_li / sh_lt reused by the next chunk
     }
     if (threadIdx.x == 0 && c_ns > 0) {
