@@ -61,6 +61,18 @@ def window_sizes(batch, gap_days: float = 0.5) -> np.ndarray:
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch, budget_s: float = 15.0):
     """The oracle as it stands, on the host's cores, over the first curves of
     the same workload (about `budget_s` seconds)."""
@@ -79,7 +91,8 @@ def cpu_baseline(batch, budget_s: float = 15.0):
     dt = time.perf_counter() - t0
     windows = int(np.isfinite(tr).sum())
     return {"value": windows / dt, "unit": "window-estimates/s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
+            "per_core": windows / dt / max(1, int(cores)),
             "sample": "first %d of the %d curves (%d windows), FP64 C oracle, %d threads, %.1f s"
                       % (n, batch.n_curves, windows, cores, dt)}
 
