@@ -32,7 +32,7 @@ import itertools
 import threading
 import time as _time
 from collections import deque
-from concurrent.futures import Future
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -248,8 +248,12 @@ class GpuExecutor:
     """Resident device arrays, a copy stream and a compute stream, pinned
     staging rings, and a replayable plan over the arrays."""
 
+    # Host copies into and out of pinned staging are split over a few threads
+    # once a group is this large (numpy releases the GIL while it copies).
+    PARALLEL_COPY_SAMPLES = 1 << 19
+
     def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device=0,
-                 staging_bytes: int = 4 << 30):
+                 staging_bytes: int = 4 << 30, copy_threads: int = 4):
         import torch
 
         from . import _lib
@@ -267,6 +271,29 @@ class GpuExecutor:
         self.max_W = int(max_W)
         self.ring_in = PinnedRing(torch, staging_bytes)        # flux + time of admitted groups
         self.ring_out = PinnedRing(torch, staging_bytes // 3)  # trend of finished steps
+        self.copy_threads = max(1, int(copy_threads))
+        self._pool = (ThreadPoolExecutor(self.copy_threads, thread_name_prefix="umi-copy")
+                      if self.copy_threads > 1 else None)
+
+    def _run_split(self, n, items, work):
+        """Run work(chunk) over `items` ((start, ...) tuples covering n samples
+        in order), split into contiguous chunks of about equal samples over the
+        copy threads when n is large."""
+        if self._pool is None or n < self.PARALLEL_COPY_SAMPLES or len(items) < 2:
+            work(items)
+            return
+        k = min(self.copy_threads, len(items))
+        bounds = [n * (i + 1) // k for i in range(k)]
+        chunks, cur, b = [], [], 0
+        for it in items:
+            cur.append(it)
+            if it[0] + it[1].size >= bounds[b] and b < k - 1:
+                chunks.append(cur)
+                cur, b = [], b + 1
+        if cur:
+            chunks.append(cur)
+        for f in [self._pool.submit(work, c) for c in chunks]:
+            f.result()
 
     def _pinned(self, ring, nbytes):
         got = ring.alloc(nbytes)
@@ -285,11 +312,16 @@ class GpuExecutor:
         # layout: time first (8-byte aligned), then flux
         tview = mem[:8 * n].view(np.float64)
         fview = mem[8 * n:12 * n].view(np.float32)
-        pos = 0
+        items, pos = [], 0
         for f, t in parts:
-            fview[pos:pos + f.size] = f
-            tview[pos:pos + f.size] = t
+            items.append((pos, f, t))
             pos += f.size
+
+        def copy(chunk):
+            for p0, f, t in chunk:
+                fview[p0:p0 + f.size] = f
+                tview[p0:p0 + f.size] = t
+        self._run_split(n, items, copy)
         with torch.cuda.stream(self.copy_stream):
             self.time[offset:offset + n].copy_(tbuf[:8 * n].view(torch.float64), non_blocking=True)
             self.flux[offset:offset + n].copy_(tbuf[8 * n:12 * n].view(torch.float32),
@@ -337,7 +369,15 @@ class GpuExecutor:
         handle[0].synchronize()
         res = []
         for tok, _, arr in handle[1]:
-            res.append(arr.copy())  # the ring block is reused right away
+            out = np.empty_like(arr)  # the ring block is reused right away
+            step = max(1, -(-arr.size // self.copy_threads))
+            pieces = [(a, arr[a:a + step]) for a in range(0, arr.size, step)]
+
+            def copy(chunk, out=out):
+                for a, src in chunk:
+                    out[a:a + src.size] = src
+            self._run_split(arr.size, pieces, copy)
+            res.append(out)
             if tok is not None:
                 self.ring_out.release(tok)
         for tok in handle[2]:  # the step is done, so its uploads are too
@@ -347,6 +387,8 @@ class GpuExecutor:
 
     def close(self):
         self.plan.destroy()
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
 
 
 class FakeExecutor:
