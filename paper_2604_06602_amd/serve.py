@@ -440,11 +440,17 @@ class FakeExecutor:
 
 
 class Server:
+    # Samples per step (and per admission group): bounds the pinned staging a
+    # step needs, so the executor's rings always have room (a lone request
+    # larger than this still forms a step of its own).
+    MAX_STEP_SAMPLES = 1 << 25
+
     def __init__(self, executor, max_step_curves: int | None = None, max_inflight: int = 2,
-                 clock=_time.perf_counter):
+                 clock=_time.perf_counter, max_step_samples: int | None = None):
         self.ex = executor
         self.arena = Arena(executor.capacity)
         self.max_step_curves = int(max_step_curves or getattr(executor, "max_curves", 4096))
+        self.max_step_samples = int(max_step_samples or self.MAX_STEP_SAMPLES)
         self.max_inflight = max_inflight
         self.max_W = int(getattr(executor, "max_W", 2047))
         self.clock = clock
@@ -452,7 +458,8 @@ class Server:
         self._ids = itertools.count()
         self._lock = threading.Condition()
         self._waiting: deque = deque()   # submitted, not admitted
-        self._groups: list = []           # admitted, not launched
+        self._groups: list = []           # admitted and uploaded, not launched
+        self._to_upload: deque = deque()  # admitted, upload not started
         self._inflight: deque = deque()   # launched steps, oldest first
         self._closing = False
         self._error: BaseException | None = None
@@ -539,7 +546,8 @@ class Server:
         for req in admitted:
             g = groups[-1] if groups else None
             if (g is not None and g.key == req.key and g.offset + g.size == req.offset
-                    and len(g.requests) < self.max_step_curves):
+                    and len(g.requests) < self.max_step_curves
+                    and g.size + req.n <= self.max_step_samples):
                 g.requests.append(req)
                 g.size += req.n
             else:
@@ -560,11 +568,13 @@ class Server:
         if not self._groups:
             return None
         key = self._groups[0].key
-        chosen, n = [], 0
-        for g in self._groups:  # groups never exceed max_step_curves (see _admit)
-            if g.key == key and n + len(g.requests) <= self.max_step_curves:
+        chosen, n, samples = [], 0, 0
+        for g in self._groups:  # groups respect both limits on their own (see _admit)
+            if (g.key == key and n + len(g.requests) <= self.max_step_curves
+                    and (not chosen or samples + g.size <= self.max_step_samples)):
                 chosen.append(g)
                 n += len(g.requests)
+                samples += g.size
         for g in chosen:
             self._groups.remove(g)
         return Step(chosen)
@@ -633,7 +643,16 @@ class Server:
                     while self._inflight and self.ex.ready(self._inflight[0].handle):
                         self._finish(self._inflight.popleft())
                     t1 = clk()
-                    groups = self._admit()
+                    self._to_upload.extend(self._admit())
+                    # stage uploads ahead of launch, but no more than two
+                    # steps' worth: pinned staging stays bounded under backlog
+                    staged = sum(g.size for g in self._groups)
+                    groups = []
+                    while self._to_upload and (not groups and not self._groups
+                                               or staged < 2 * self.max_step_samples):
+                        g = self._to_upload.popleft()
+                        groups.append(g)
+                        staged += g.size
                     t2 = clk()
                 self._upload(groups)
                 t3 = clk()
@@ -650,7 +669,7 @@ class Server:
                     ph["upload"] += t3 - t2
                     ph["launch"] += t4 - t3
                     self.stats.loop_max_s = max(self.stats.loop_max_s, t4 - t0)
-                    idle = not self._inflight and not self._groups
+                    idle = not self._inflight and not self._groups and not self._to_upload
                     if idle and not self._waiting and self._closing:
                         return
                     if idle and not self._waiting:

@@ -282,3 +282,24 @@ def test_split_copies_cover_every_sample_once():
         run(n, items, work)
         assert np.array_equal(dst, np.concatenate(parts))
     _E._pool.shutdown()
+
+
+def test_steps_respect_the_sample_limit_and_big_requests_still_run():
+    """Groups and steps stay within max_step_samples, except a lone request
+    larger than the limit, which forms a step of its own."""
+    seen = []
+
+    class Checking(FakeExecutor):
+        def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
+            seen.append(sum(lengths))
+            return super().launch(offsets, lengths, Ws, alphas, cs, iters, uploads, ranges)
+    srv = Server(Checking(100000, delay=0.002), max_step_samples=1000)
+    futs = [srv.submit(np.ones(300, np.float32), W=5) for _ in range(20)]
+    big = srv.submit(np.ones(2500, np.float32), W=5)
+    futs += [srv.submit(np.ones(300, np.float32), W=5) for _ in range(10)]
+    for fu in futs + [big]:
+        fu.result(timeout=10)
+    srv.close()
+    assert 2500 in seen
+    assert all(s <= 1000 for s in seen if s != 2500)
+    assert sum(seen) == 30 * 300 + 2500
