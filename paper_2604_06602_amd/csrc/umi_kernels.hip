@@ -355,50 +355,43 @@ __device__ __forceinline__ uint32_t wavelet_count_less(const MainSmem& sm, int l
     return cnt;
 }
 
-// Phase 3 sweep over one window: returns sum(w) and sum(w*u) for the
-// current location, where u = x*k + b = (x - mu)/(c s).  kMin selects the
-// asymmetric branch as min(u, alpha*u) (alpha >= 1) or max (alpha < 1): both
-// equal alpha*u for u < 0 and u for u >= 0 (Eq. 2).
-// Phase 3 sweep over the n samples xv[c0], ..., xv[c0 + n - 1] of one
-// window: returns sum(w) and sum(w*u) for the current location, with
-// u = x*k + b = (x - mu)/(c s).  kMin selects the asymmetric branch as
-// min(u, alpha*u) (alpha >= 1) or max (alpha < 1): both equal alpha*u for
-// u < 0 and u for u >= 0 (Eq. 2).  The samples are summed in index order
-// whatever the launch shape, so results do not depend on the tiling.
-// `n` may be a per-lane count or a wave-uniform one; with a uniform count
-// the loop runs on the scalar unit and only the LDS address stays per lane.
-template <bool kMin>
-__device__ __forceinline__ void bisquare_sums(const float* __restrict__ xv, int c0, int n,
-                                              float k, float b, float alpha, float& sw_out,
-                                              float& swu_out)
+// Phase 3 (Eqs. 2-4) with the asymmetry folded into one fma.  With
+// u = (x - mu)/(c s), A = (1 + alpha)/2 and B = (1 - alpha)/2, the effective
+// residual of Eq. 2 is A u + B |u| (u for u >= 0, alpha u for u < 0, any
+// alpha > 0).  In the scaled variable v = A u = x*k + b, k = A/(c s), it is
+// v + beta |v| with beta = B/A, one fma with an |.| source modifier.  The
+// sums are sum(w) and sum(w v); Eq. 4 in residual form is then
+// mu + sum(w v) / (k sum(w)).
+__device__ __forceinline__ void bisquare_acc(float x, float k, float b, float beta, float& sw,
+                                             float& swv)
 {
-    float sw = 0.0f, swu = 0.0f;
-    const float* x = xv + c0;
-#pragma unroll 8
-    for (int j = 0; j < n; ++j) {
-        const float u = __builtin_fmaf(x[j], k, b);
-        const float au = alpha * u;
-        const float ue = kMin ? __builtin_fminf(u, au) : __builtin_fmaxf(u, au);
-        // Eq. 3: (1 - ue^2)^2 on |ue| < 1, else 0.  1 - ue^2 <= 1 always, so
-        // clamping to [0, 1] is exactly max(., 0).
-        const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
-        sw = __builtin_fmaf(t, t, sw);
-        swu = __builtin_fmaf(t * t, u, swu);
-    }
-    sw_out = sw;
-    swu_out = swu;
+    const float v = __builtin_fmaf(x, k, b);
+    const float ue = __builtin_fmaf(__builtin_fabsf(v), beta, v);
+    // Eq. 3: (1 - ue^2)^2 on |ue| < 1, else 0.  1 - ue^2 <= 1 always, so
+    // clamping to [0, 1] is exactly max(., 0).
+    const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
+    const float w = t * t;
+    sw += w;
+    swv = __builtin_fmaf(w, v, swv);
 }
 
-template <bool kMin>
+// Phase 3 over the n samples xv[c0], ..., xv[c0 + n - 1] of one window, from
+// the median m with the scaled k above.  The samples are summed in index
+// order whatever the launch shape, so results do not depend on the tiling.
+// `n` may be a per-lane count or a wave-uniform one; with a uniform count
+// the loop runs on the scalar unit and only the LDS address stays per lane.
 __device__ __forceinline__ float bisquare(const float* __restrict__ xv, int c0, int n, float m,
-                                          float k, float alpha, int iters)
+                                          float k, float beta, int iters)
 {
     float mu = m;
+    const float* x = xv + c0;
     for (int it = 0; it < iters; ++it) {
-        float sw, swu;
-        bisquare_sums<kMin>(xv, c0, n, k, -mu * k, alpha, sw, swu);
+        const float b = -mu * k;
+        float sw = 0.0f, swv = 0.0f;
+#pragma unroll 8
+        for (int j = 0; j < n; ++j) bisquare_acc(x[j], k, b, beta, sw, swv);
         if (!(sw > 0.0f)) break;  // no weight left: keep mu
-        mu = mu + swu / (sw * k);  // Eq. 4 in residual form
+        mu = mu + swv / (sw * k);
     }
     return mu;
 }
@@ -416,59 +409,45 @@ __device__ __forceinline__ float upper_ssq(const float* __restrict__ xv, int c0,
     return ssq;
 }
 
-// Accumulate one sample into a window's Phase 3 sums (same arithmetic as
-// bisquare_sums).
-template <bool kMin>
-__device__ __forceinline__ void bisquare_acc(float x, float k, float b, float alpha, float& sw,
-                                             float& swu)
-{
-    const float u = __builtin_fmaf(x, k, b);
-    const float au = alpha * u;
-    const float ue = kMin ? __builtin_fminf(u, au) : __builtin_fmaxf(u, au);
-    const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-ue, ue, 1.0f), 0.0f, 1.0f);
-    sw = __builtin_fmaf(t, t, sw);
-    swu = __builtin_fmaf(t * t, u, swu);
-}
-
 // R windows that start at consecutive compacted samples x[0], x[1], ...,
 // x[R-1], each n samples long (n >= R): one LDS read feeds every window that
 // contains the sample, and each window still sums its samples in index
 // order, so the result equals R single-window sweeps bit for bit.
-template <int R, bool kMin>
+template <int R>
 __device__ __forceinline__ void bisquare_multi(const float* __restrict__ x, int n, const float* k,
-                                               float* mu, bool* act, float alpha, int iters)
+                                               float* mu, bool* act, float beta, int iters)
 {
     for (int it = 0; it < iters; ++it) {
-        float b[R], sw[R], swu[R];
+        float b[R], sw[R], swv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             b[r] = -mu[r] * k[r];
             sw[r] = 0.0f;
-            swu[r] = 0.0f;
+            swv[r] = 0.0f;
         }
 #pragma unroll
         for (int j = 0; j < R - 1; ++j) {  // head: windows 0..j
             const float xj = x[j];
 #pragma unroll
-            for (int r = 0; r <= j; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+            for (int r = 0; r <= j; ++r) bisquare_acc(xj, k[r], b[r], beta, sw[r], swv[r]);
         }
 #pragma unroll 8
         for (int j = R - 1; j < n; ++j) {  // every window
             const float xj = x[j];
 #pragma unroll
-            for (int r = 0; r < R; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+            for (int r = 0; r < R; ++r) bisquare_acc(xj, k[r], b[r], beta, sw[r], swv[r]);
         }
 #pragma unroll
         for (int d = 1; d < R; ++d) {  // tail: windows d..R-1 take sample n-1+d
             const float xj = x[n - 1 + d];
 #pragma unroll
-            for (int r = d; r < R; ++r) bisquare_acc<kMin>(xj, k[r], b[r], alpha, sw[r], swu[r]);
+            for (int r = d; r < R; ++r) bisquare_acc(xj, k[r], b[r], beta, sw[r], swv[r]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (act[r]) {
                 if (sw[r] > 0.0f)
-                    mu[r] = mu[r] + swu[r] / (sw[r] * k[r]);  // Eq. 4 in residual form
+                    mu[r] = mu[r] + swv[r] / (sw[r] * k[r]);
                 else
                     act[r] = false;  // no weight left: keep mu from now on
             }
@@ -688,13 +667,15 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
     }
     float k[R], mu[R];
     bool act[R];
+    const float kA = 0.5f * (1.0f + alpha);         // A of the folded residual
+    const float beta = (1.0f - alpha) / (1.0f + alpha);  // B / A
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         mu[r] = m[r];
         k[r] = 0.0f;
         act[r] = false;
         if (live[r] && sc[r] > 0.0f && iters > 0) {
-            const float kk = 1.0f / (c * sc[r]);
+            const float kk = kA / (c * sc[r]);
             if (isfinite(kk)) {
                 k[r] = kk;
                 act[r] = true;
@@ -702,18 +683,12 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         }
     }
     // Phase 3 (Eqs. 2-4)
-    if (alpha >= 1.0f) {
-        if (uniform) {
-            bisquare_multi<R, true>(sm.xv + ca[0], (int)n_u, k, mu, act, alpha, iters);
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (act[r]) mu[r] = bisquare<true>(sm.xv, (int)ca[r], (int)n[r], m[r], k[r], alpha, iters);
-        }
+    if (uniform) {
+        bisquare_multi<R>(sm.xv + ca[0], (int)n_u, k, mu, act, beta, iters);
     } else {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (act[r]) mu[r] = bisquare<false>(sm.xv, (int)ca[r], (int)n[r], m[r], k[r], alpha, iters);
+            if (act[r]) mu[r] = bisquare(sm.xv, (int)ca[r], (int)n[r], m[r], k[r], beta, iters);
     }
     const float nanf_ = __builtin_nanf("");
 #pragma unroll

@@ -139,13 +139,15 @@ def test_plan_run_ex_equals_gather_ex(torch, umi):
                 trend.fill_(-1.0)
                 det.fill_(-1.0)
                 torch.cuda.synchronize()
-                plan.run(offs, b.lengths, b.W, alpha=alphas, c=cs, scale=sc, detrended=det)
+                wd = np.where(np.arange(b.n_curves) % 3 == 0, 0.4, 0.0) if rep == 2 else None
+                plan.run(offs, b.lengths, b.W, alpha=alphas, c=cs, scale=sc, detrended=det,
+                         window_days=wd)
                 stream.synchronize()
                 p_tr, p_det = trend.cpu().numpy(), det.cpu().numpy()
                 r_tr = torch.full((cap,), -1.0, dtype=torch.float32, device="cuda")
                 r_det = torch.full((cap,), -1.0, dtype=torch.float32, device="cuda")
                 umi.detrend_gather_into(flux, time, offs, b.lengths, b.W, r_tr, alpha=alphas,
-                                        c=cs, scale=sc, detrended=r_det)
+                                        c=cs, scale=sc, detrended=r_det, window_days=wd)
                 torch.cuda.synchronize()
                 assert np.array_equal(p_tr.view(np.uint32), r_tr.cpu().numpy().view(np.uint32)), (rep, sc)
                 assert np.array_equal(p_det.view(np.uint32), r_det.cpu().numpy().view(np.uint32)), (rep, sc)

@@ -163,6 +163,24 @@ def test_config_full_size_sampled(torch, umi, oracle_lib, cfg):
         assert np.array_equal(np.isnan(g_tr[off[ci]:off[ci] + f.size]), lo < 0)
 
 
+def test_one_long_curve(torch, umi, oracle_lib):
+    """A single 12-million-sample curve (about two years at 2-min cadence) in
+    one call: thousands of tiles of one curve, 64-bit sample offsets inside
+    the packed arrays, sampled against the oracle."""
+    rng = np.random.default_rng(31)
+    n = 12_000_000
+    t = np.arange(n, dtype=np.float64) * (2 / 1440)
+    f = (1 + 1e-3 * rng.standard_normal(n) + 2e-3 * np.sin(2 * np.pi * t / 3.3)).astype(np.float32)
+    f[5_000_000:5_001_000] = np.nan
+    t[8_000_000:] += 0.8                                   # a segment break
+    g_tr, g_md = run_batch(torch, umi, f, t, [n], [361])
+    idx = np.unique(np.concatenate([[0, 1, 4_999_999, 5_001_000, 7_999_999, 8_000_000, n - 1],
+                                    rng.integers(0, n, 200)]))
+    o_tr, o_md = oracle_lib.detrend_at(f, t, 361, idx)
+    assert_parity(g_tr[idx], g_md[idx], o_tr, o_md, what="12M-sample curve")
+    assert np.isnan(g_tr[5_000_000:5_001_000]).all() and np.isfinite(g_tr[:5_000_000]).all()
+
+
 def edge_case_batch():
     """Empty, tiny, all-invalid, dead-segment, invalid-time, tied, signed-zero,
     constant, negative, large-offset, W=1, sparse and largest-W curves."""
