@@ -714,20 +714,29 @@ def run_open_loop(server: Server, curves, arrivals, keep_results=None, pause_gc=
 
 
 def _open_loop(server, curves, arrivals, keep_results):
+    # Results are taken as they complete and dropped unless kept, as a client
+    # would: holding every result of a minute at 20,000 curves/s would pin
+    # about 100 GB of host memory and stall both threads in page faults.
     t0 = server.clock()
-    futs = []
+    pending = deque()
+    kept = {}
+
+    def drain(wait):
+        while pending and (wait or pending[0][1].done()):
+            i, fu = pending.popleft()
+            res = fu.result()
+            if keep_results is not None and keep_results(i):
+                kept[i] = (i % len(curves), res)
+
     for i, at in enumerate(arrivals):
         target = t0 + float(at)
+        drain(False)
         while True:
             now = server.clock()
             if now >= target:
                 break
             _time.sleep(min(target - now, 0.001))
         f, t, W = curves[i % len(curves)]
-        futs.append(server.submit(f, t, W, arrival=target))
-    kept = {}
-    for i, fu in enumerate(futs):
-        res = fu.result()
-        if keep_results is not None and keep_results(i):
-            kept[i] = (i % len(curves), res)
+        pending.append((i, server.submit(f, t, W, arrival=target)))
+    drain(True)
     return server.summary(), kept
