@@ -526,19 +526,11 @@ __device__ __forceinline__ float window_mad(const MainSmem& sm, int levels, uint
     return mad;
 }
 
-// Phase 1 for a full window of W <= kSmallW samples whose totalOrder keys sit
-// at kp[0 .. W): a bitonic network over 32 registers (padded with the largest
-// key) sorts them, the element of rank (W-1)/2 is the median, and the points
-// strictly above it are counted on the unsorted keys.  Same results as the
-// tile-sort path, without the tile sort and wavelet matrix.
 constexpr int kSmallW = 31;
 
-__device__ __forceinline__ void small_window_median(const uint32_t* __restrict__ kp, int W,
-                                                    float& m, uint32_t& nplus)
+// Sort 32 keys in registers ascending (bitonic network).
+__device__ __forceinline__ void sort32(uint32_t (&k)[32])
 {
-    uint32_t k[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) k[i] = i < W ? kp[i] : 0xffffffffu;
 #pragma unroll
     for (int kk = 2; kk <= 32; kk <<= 1) {
 #pragma unroll
@@ -555,16 +547,57 @@ __device__ __forceinline__ void small_window_median(const uint32_t* __restrict__
             }
         }
     }
+}
+
+// Phase 1 for up to three consecutive full windows kp[r .. r + W), r < nwin,
+// of W <= kSmallW samples given by their totalOrder keys.  The W - 2 keys the
+// three share, kp[2 .. W), are sorted once (padded with the largest key); each
+// window is that core plus two keys lo <= hi, and its element of rank
+// q = (W-1)/2 is min(A[q], max(A[q-1], lo), max(A[q-2], hi)) for the sorted
+// core A (an index below 0 reads as the smallest key): the rank-q element of
+// a union of two sorted lists, split over the at most two keys of the second.
+// The points strictly above each median are counted on the unsorted keys.
+// Keys past kp[lim] are never read.  Same results as the tile-sort path,
+// without the tile sort and wavelet matrix.
+__device__ __forceinline__ void small_window_medians(const uint32_t* __restrict__ kp, int W,
+                                                     int nwin, int lim, float* pm, uint32_t* pn)
+{
     const int q = (W - 1) >> 1;  // <= 15, the same for the whole tile
-    uint32_t mk = k[0];
+    uint32_t med[3];
+    if (W == 1) {
 #pragma unroll
-    for (int i = 1; i < 16; ++i) mk = q == i ? k[i] : mk;
-    m = key_value(mk);
-    // strictly above, numerically: -0 and +0 are equal
-    const uint32_t T = m == 0.0f ? order_key(0.0f) : mk;
-    uint32_t cnt = 0;
-    for (int j = 0; j < W; ++j) cnt += kp[j] > T ? 1u : 0u;
-    nplus = cnt;
+        for (int r = 0; r < 3; ++r) med[r] = kp[min(r, lim)];
+    } else {
+        uint32_t k[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) k[i] = i < W - 2 ? kp[2 + i] : 0xffffffffu;
+        sort32(k);
+        uint32_t a0 = k[0], a1 = 0u, a2 = 0u;  // A[q], A[q-1], A[q-2]
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            a0 = q == i ? k[i] : a0;
+            a1 = q - 1 == i ? k[i] : a1;
+            a2 = q - 2 == i ? k[i] : a2;
+        }
+        const uint32_t ex[4] = {kp[0], kp[1], kp[min(W, lim)], kp[min(W + 1, lim)]};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const uint32_t lo = min(ex[r], ex[r + 1]), hi = max(ex[r], ex[r + 1]);
+            med[r] = min(a0, min(max(a1, lo), max(a2, hi)));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        if (r < nwin) {
+            const float m = key_value(med[r]);
+            // strictly above, numerically: -0 and +0 are equal
+            const uint32_t T = m == 0.0f ? order_key(0.0f) : med[r];
+            uint32_t cnt = 0;
+            for (int j = 0; j < W; ++j) cnt += kp[r + j] > T ? 1u : 0u;
+            pm[r] = m;
+            pn[r] = cnt;
+        }
+    }
 }
 
 // The windows of one tile: each lane takes R consecutive output positions.
@@ -861,10 +894,10 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         uint32_t pn[3] = {0u, 0u, 0u};
         if (simple) {
             const uint32_t* keys = reinterpret_cast<const uint32_t*>(sm.seq);
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int p = t0 + tid * R + r;
-                if (r < R && p < t1) small_window_median(keys + (p - h - s0), cd.W, pm[r], pn[r]);
+            const int p0 = t0 + tid * R;
+            if (p0 < t1) {
+                const int b = p0 - h - s0;
+                small_window_medians(keys + b, cd.W, min(R, t1 - p0), N - 1 - b, pm, pn);
             }
         }
         if (R == 3)

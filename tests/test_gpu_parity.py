@@ -230,7 +230,9 @@ def test_edge_cases(torch, umi, oracle_lib):
 
 def test_small_window_network_path(torch, umi, oracle_lib):
     """Tiles whose windows are all full and W <= 31 take their medians from
-    per-window networks: every odd W up to 31 (and 33, just beyond), heavy
+    a register network over each lane's shared core of keys, under several
+    tile sizes (three, two or one windows per lane, and ragged last lanes):
+    every odd W up to 31 (and 33, just beyond), heavy
     ties, signed zeros and constant runs, with and without invalid samples
     (which send tiles back to the general path) -- median bit-exact, trend
     within tolerance."""
@@ -249,11 +251,19 @@ def test_small_window_network_path(torch, umi, oracle_lib):
     packed = synth.lightcurves.pack(curves)
     mag = window_magnitude(packed.flux, packed.time, packed.lengths, packed.W, oracle_lib)
     for a, c in [(2.0, 5.0), (10.0, 2.5)]:
-        g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths, packed.W,
-                               alpha=a, c=c)
         o_tr, o_md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W,
                                               alpha=a, c=c)
-        assert_parity(g_tr, g_md, o_tr, o_md, what="small W a=%g" % a, scale=mag)
+        # default tiles (three windows per lane), then tiles whose last lanes
+        # hold two, and tiles of two and of one window per lane
+        for table in [None, "31 1100 4", "31 700 4", "31 300 4"]:
+            umi.set_tuning(table)
+            try:
+                g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths,
+                                       packed.W, alpha=a, c=c)
+            finally:
+                umi.set_tuning(None)
+            assert_parity(g_tr, g_md, o_tr, o_md, what="small W a=%g tiles %s" % (a, table),
+                          scale=mag)
 
 
 def test_no_time_array(torch, umi, oracle_lib):
