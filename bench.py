@@ -163,7 +163,8 @@ def measured_fma_peak(torch, stream, log, iters=40000, launches=10):
 SERVE_POOL = 1000  # distinct curves drawn like the mixed workload, cycled by arrivals
 
 
-def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=50):
+def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=50,
+                copy_threads=4):
     """Open-loop serving: Poisson arrivals (rate curves/s) of curves drawn like
     the mixed workload, device-memory budget `budget_gb`; latency from the
     scheduled arrival to the result in host memory."""
@@ -173,7 +174,7 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
     pool = [synth.curve_for(4, i) for i in range(SERVE_POOL)]
     capacity = int(budget_gb * 1e9) // BYTES_PER_SAMPLE
     results = []
-    ex = GpuExecutor(capacity, max_curves=4096, max_W=721)
+    ex = GpuExecutor(capacity, max_curves=4096, max_W=721, copy_threads=copy_threads)
     srv = Server(ex)
     for i in range(8):  # warm up: capture both graph slots, touch the pinned pool
         srv.submit(*pool[i]).result()
@@ -235,6 +236,8 @@ def main(argv=None):
                          "at each --rates value (curves/s) for --serve-seconds each")
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-threads", type=int, default=4,
+                    help="host threads for pinned staging and result copies in serving")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--no-serve-leg", action="store_true",
                     help="skip the short serving measurement of the default run")
@@ -269,7 +272,7 @@ def main(argv=None):
     if args.serve:
         rates = [float(r) for r in args.rates.split(",")]
         out = serve_sweep(rates, args.serve_seconds, args.budget_gb, log,
-                          check_oracle=not args.no_cpu_baseline)
+                          check_oracle=not args.no_cpu_baseline, copy_threads=args.copy_threads)
         print(json.dumps(out), flush=True)
         return 0
 

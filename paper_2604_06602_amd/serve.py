@@ -149,6 +149,8 @@ class Stats:
     service: list = field(default_factory=list)    # launched -> result in host memory
     step_curves: list = field(default_factory=list)
     loop_max_s: float = 0.0                          # longest scheduler iteration
+    loop_max_phases: dict = field(default_factory=dict)  # and how it was spent
+    step_samples_max: int = 0
     phase_s: dict = field(default_factory=lambda: {"finish": 0.0, "admit": 0.0,
                                                    "upload": 0.0, "launch": 0.0})
     submit_lag: list = field(default_factory=list)  # arrival -> submit() called
@@ -181,6 +183,9 @@ class Stats:
         lag = np.array(self.submit_lag) if self.submit_lag else np.zeros(0)
         out["submit_lag_p99_ms"] = float(np.percentile(lag, 99) * 1e3) if lag.size else None
         out["scheduler_longest_iteration_ms"] = self.loop_max_s * 1e3
+        out["scheduler_longest_iteration_phases_ms"] = {
+            k: v * 1e3 for k, v in self.loop_max_phases.items()}
+        out["largest_step_samples"] = self.step_samples_max
         out["scheduler_phase_s"] = dict(self.phase_s)
         if arena is not None:
             out["arena_high_water_samples"] = arena.high_water
@@ -272,6 +277,7 @@ class GpuExecutor:
         self.ring_in = PinnedRing(torch, staging_bytes)        # flux + time of admitted groups
         self.ring_out = PinnedRing(torch, staging_bytes // 3)  # trend of finished steps
         self.copy_threads = max(1, int(copy_threads))
+        self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
         self._pool = (ThreadPoolExecutor(self.copy_threads, thread_name_prefix="umi-copy")
                       if self.copy_threads > 1 else None)
 
@@ -298,6 +304,7 @@ class GpuExecutor:
     def _pinned(self, ring, nbytes):
         got = ring.alloc(nbytes)
         if got is None:  # ring full: a one-off pinned block
+            self.pinned_fallbacks += 1
             t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, pin_memory=True)
             return None, t, t.numpy()
         tok, start = got
@@ -516,7 +523,9 @@ class Server:
 
     def summary(self) -> dict:
         with self._lock:
-            return self.stats.summary(self.arena)
+            out = self.stats.summary(self.arena)
+            out["pinned_fallbacks"] = getattr(self.ex, "pinned_fallbacks", None)
+            return out
 
     def reset_stats(self):
         """Start a new measurement window (e.g. after a warm-up)."""
@@ -593,6 +602,8 @@ class Server:
             step.launched_at = now
             self.stats.steps += 1
             self.stats.step_curves.append(len(reqs))
+            self.stats.step_samples_max = max(self.stats.step_samples_max,
+                                              sum(g.size for g in step.groups))
             return True
         except Exception as e:  # a failed step fails only its own requests
             self._finish(step, error=e)
@@ -668,7 +679,10 @@ class Server:
                     ph["admit"] += t2 - t1
                     ph["upload"] += t3 - t2
                     ph["launch"] += t4 - t3
-                    self.stats.loop_max_s = max(self.stats.loop_max_s, t4 - t0)
+                    if t4 - t0 > self.stats.loop_max_s:
+                        self.stats.loop_max_s = t4 - t0
+                        self.stats.loop_max_phases = {"finish": t1 - t0, "admit": t2 - t1,
+                                                      "upload": t3 - t2, "launch": t4 - t3}
                     idle = not self._inflight and not self._groups and not self._to_upload
                     if idle and not self._waiting and self._closing:
                         return
