@@ -1,0 +1,44 @@
+/*
+ * umi_serve.h -- host-side helper of the UMI serving loop (libumi.so).
+ *
+ * Not a step of the method (arXiv 2604.06602, Section 2): the serving loop
+ * batches many curves per device step, and each step stages every curve's
+ * flux and time into pinned host memory before one host-to-device copy, and
+ * copies each result back out of pinned memory afterwards.  Done curve by
+ * curve from an interpreter, those copies cost more in per-call overhead and
+ * lock hand-offs than in bytes moved; this entry point does a whole list of
+ * them in one call, split over a small pool of native threads.
+ */
+#ifndef UMI_SERVE_H
+#define UMI_SERVE_H
+
+#include <stdint.h>
+
+#include "umi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UMI_HOST_COPY_MAX_THREADS 64
+
+/* Host-to-host copies: for i in [0, n), bytes[i] bytes from src[i] to dst[i].
+ * All pointers, including the three arrays themselves, are [host] memory
+ * (pageable or pinned) owned by the caller; no device memory and no stream are
+ * involved, and the call returns when every copy is complete.  The copies are
+ * cut into pieces of at most 1 MiB, which up to `threads` threads (the calling
+ * thread and threads - 1 pool threads, started on first use and kept for the
+ * life of the process) take in turn.  The regions of different copies must not
+ * overlap (the result is then undefined, as for memcpy).  Calls from several
+ * threads are safe; they run one after another.
+ * Errors: n < 0, threads < 1 or > UMI_HOST_COPY_MAX_THREADS, a NULL array with
+ * n > 0, a negative size, or a NULL pointer with a positive size give
+ * UMI_ERR_INVALID_ARG before anything is copied.  n = 0 is a no-op. */
+umi_status umi_host_copy_many(void* const* dst, const void* const* src, const int64_t* bytes,
+                              int64_t n, int32_t threads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UMI_SERVE_H */

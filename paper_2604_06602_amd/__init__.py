@@ -20,6 +20,7 @@ from ._lib import (  # noqa: F401
     detrend_batch,
     detrend_batch_into,
     detrend_gather_into,
+    host_copy_many,
     last_error,
     release,
     set_tuning,

@@ -104,6 +104,8 @@ def _load():
     lib.umi_version.argtypes = []
     lib.umi_debug_inject_error.restype = None
     lib.umi_debug_inject_error.argtypes = [ctypes.c_int]
+    lib.umi_host_copy_many.restype = ctypes.c_int
+    lib.umi_host_copy_many.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32]
     return lib
 
 
@@ -113,6 +115,19 @@ lib = _load()
 def _check(status: int):
     if status != UMI_OK:
         raise UmiError(status, lib.umi_last_error().decode(errors="replace"))
+
+
+def host_copy_many(dst_ptrs, src_ptrs, nbytes, threads: int = 1):
+    """Host-to-host copies nbytes[i] from src_ptrs[i] to dst_ptrs[i] (int64
+    arrays of addresses and sizes) in one native call, which runs without the
+    interpreter lock and splits the work over `threads` native threads."""
+    d = np.ascontiguousarray(dst_ptrs, np.uint64)
+    s = np.ascontiguousarray(src_ptrs, np.uint64)
+    b = np.ascontiguousarray(nbytes, np.int64)
+    if not (d.shape == s.shape == b.shape and b.ndim == 1):
+        raise ValueError("host_copy_many: three 1-D arrays of equal length")
+    _check(lib.umi_host_copy_many(d.ctypes.data, s.ctypes.data, b.ctypes.data, b.size,
+                                  int(threads)))
 
 
 def last_error() -> str:

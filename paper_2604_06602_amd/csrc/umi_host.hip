@@ -1,9 +1,11 @@
 // Host side of the UMI C ABI (include/umi.h): argument checks, the batch
 // packer (cost-sorted curve table), per-(device, stream) workspaces, the
-// tuning table, the kernel launches, and replayable plans (hipGraph).
+// tuning table, the kernel launches, replayable plans (hipGraph), and the
+// serving loop's batched host copies (include/umi_serve.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -12,11 +14,14 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
+#include <condition_variable>
 
 #include "umi.h"
 #include "umi_internal.h"
+#include "umi_serve.h"
 
 namespace umi {
 
@@ -492,6 +497,99 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     return UMI_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// batched host copies (umi_host_copy_many)
+
+namespace {
+
+constexpr int64_t kCopyPiece = int64_t(1) << 20;  // bytes per work item
+
+// One call's copies cut into pieces; threads take pieces by an atomic index.
+struct CopyJob {
+    void* const* dst;
+    const void* const* src;
+    const int64_t* bytes;
+    std::vector<int64_t> first;  // first piece of copy i; first[n] = total pieces
+    std::atomic<int64_t> next{0};
+    int slots = 0;               // pool threads that may still join
+
+    void work()
+    {
+        const int64_t total = first.back();
+        for (;;) {
+            const int64_t p = next.fetch_add(1, std::memory_order_relaxed);
+            if (p >= total) return;
+            const size_t i = size_t(std::upper_bound(first.begin(), first.end(), p) -
+                                    first.begin()) - 1;
+            const int64_t off = (p - first[i]) * kCopyPiece;
+            const int64_t len = std::min(kCopyPiece, bytes[i] - off);
+            std::memcpy(static_cast<char*>(dst[i]) + off,
+                        static_cast<const char*>(src[i]) + off, size_t(len));
+        }
+    }
+};
+
+// Pool threads wait for a job, take pieces until none are left, and report
+// back; one job runs at a time.  The pool is never destroyed (its threads
+// stay blocked on the condition variable until the process exits).
+class CopyPool {
+  public:
+    void run(CopyJob& job, int threads)
+    {
+        std::lock_guard<std::mutex> one_at_a_time(call_mu_);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            while ((int)workers_ < threads - 1) {
+                std::thread(&CopyPool::worker, this).detach();
+                ++workers_;
+            }
+            job.slots = threads - 1;
+            job_ = &job;
+            ++gen_;
+        }
+        cv_.notify_all();
+        job.work();  // the calling thread copies too
+        std::unique_lock<std::mutex> lk(mu_);
+        job_ = nullptr;  // threads waking from now on skip this job
+        done_cv_.wait(lk, [&] { return active_ == 0; });
+    }
+
+  private:
+    void worker()
+    {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            CopyJob* j = job_;
+            if (!j || j->slots <= 0) continue;
+            --j->slots;
+            ++active_;
+            lk.unlock();
+            j->work();
+            lk.lock();
+            if (--active_ == 0) done_cv_.notify_all();
+        }
+    }
+
+    std::mutex call_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    CopyJob* job_ = nullptr;
+    uint64_t gen_ = 0;
+    int active_ = 0;
+    size_t workers_ = 0;
+};
+
+CopyPool& copy_pool()
+{
+    static CopyPool* pool = new CopyPool();  // intentionally never freed
+    return *pool;
+}
+
+}  // namespace
+
 }  // namespace umi
 
 // ---------------------------------------------------------------------------
@@ -807,5 +905,38 @@ void umi_release(void)
 const char* umi_version(void) { return "umi-mi355x 0.6.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
+
+umi_status umi_host_copy_many(void* const* dst, const void* const* src, const int64_t* bytes,
+                              int64_t n, int32_t threads)
+{
+    if (n < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: n < 0");
+    if (threads < 1 || threads > UMI_HOST_COPY_MAX_THREADS)
+        return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: threads out of range");
+    if (n == 0) return UMI_OK;
+    if (!dst || !src || !bytes)
+        return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL array");
+    umi::CopyJob job;
+    job.dst = dst;
+    job.src = src;
+    job.bytes = bytes;
+    job.first.resize(size_t(n) + 1);
+    int64_t pieces = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (bytes[i] < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: bytes < 0");
+        if (bytes[i] > 0 && (!dst[i] || !src[i]))
+            return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL pointer");
+        job.first[size_t(i)] = pieces;
+        pieces += (bytes[i] + umi::kCopyPiece - 1) / umi::kCopyPiece;
+    }
+    job.first[size_t(n)] = pieces;
+    if (pieces == 0) return UMI_OK;
+    const int64_t useful = std::min<int64_t>(threads, pieces);
+    if (useful <= 1) {
+        job.work();
+        return UMI_OK;
+    }
+    umi::copy_pool().run(job, int(useful));
+    return UMI_OK;
+}
 
 }  // extern "C"

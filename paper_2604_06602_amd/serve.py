@@ -32,7 +32,7 @@ import itertools
 import threading
 import time as _time
 from collections import deque
-from concurrent.futures import Future, ThreadPoolExecutor
+from concurrent.futures import Future
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -197,6 +197,27 @@ class Stats:
 # executors
 
 
+def _addr(a: np.ndarray) -> int:
+    return a.__array_interface__["data"][0]
+
+
+def staging_copies(parts, base: int):
+    """The copy list that stages a group's curves ((flux, time) pairs of
+    contiguous float32 / float64 arrays) at host address `base`: every time
+    array back to back first (8-byte aligned), then every flux array.
+    Returns (dst, src, nbytes, samples) for one batched native copy."""
+    k = len(parts)
+    sizes = np.fromiter((f.size for f, _ in parts), np.int64, k)
+    n = int(sizes.sum())
+    pos = np.zeros(k, np.int64)
+    np.cumsum(sizes[:-1], out=pos[1:])
+    dst = np.concatenate([base + 8 * pos, base + 8 * n + 4 * pos]).astype(np.uint64)
+    src = np.fromiter(itertools.chain((_addr(t) for _, t in parts),
+                                      (_addr(f) for f, _ in parts)), np.uint64, 2 * k)
+    nbytes = np.concatenate([8 * sizes, 4 * sizes])
+    return dst, src, nbytes, n
+
+
 class PinnedRing:
     """A preallocated pinned host buffer handed out as a ring: blocks are
     allocated at the head and released in any order; space comes back when
@@ -253,10 +274,6 @@ class GpuExecutor:
     """Resident device arrays, a copy stream and a compute stream, pinned
     staging rings, and a replayable plan over the arrays."""
 
-    # Host copies into and out of pinned staging are split over a few threads
-    # once a group is this large (numpy releases the GIL while it copies).
-    PARALLEL_COPY_SAMPLES = 1 << 19
-
     def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device=0,
                  staging_bytes: int = 4 << 30, copy_threads: int = 4):
         import torch
@@ -276,30 +293,10 @@ class GpuExecutor:
         self.max_W = int(max_W)
         self.ring_in = PinnedRing(torch, staging_bytes)        # flux + time of admitted groups
         self.ring_out = PinnedRing(torch, staging_bytes // 3)  # trend of finished steps
+        # native threads for the copies into and out of pinned staging
         self.copy_threads = max(1, int(copy_threads))
+        self._copy = _lib.host_copy_many
         self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
-        self._pool = (ThreadPoolExecutor(self.copy_threads, thread_name_prefix="umi-copy")
-                      if self.copy_threads > 1 else None)
-
-    def _run_split(self, n, items, work):
-        """Run work(chunk) over `items` ((start, ...) tuples covering n samples
-        in order), split into contiguous chunks of about equal samples over the
-        copy threads when n is large."""
-        if self._pool is None or n < self.PARALLEL_COPY_SAMPLES or len(items) < 2:
-            work(items)
-            return
-        k = min(self.copy_threads, len(items))
-        bounds = [n * (i + 1) // k for i in range(k)]
-        chunks, cur, b = [], [], 0
-        for it in items:
-            cur.append(it)
-            if it[0] + it[1].size >= bounds[b] and b < k - 1:
-                chunks.append(cur)
-                cur, b = [], b + 1
-        if cur:
-            chunks.append(cur)
-        for f in [self._pool.submit(work, c) for c in chunks]:
-            f.result()
 
     def _pinned(self, ring, nbytes):
         got = ring.alloc(nbytes)
@@ -311,24 +308,14 @@ class GpuExecutor:
         return tok, ring.buf[start:start + int(nbytes)], ring.mem[start:start + int(nbytes)]
 
     def stage_upload(self, offset: int, parts):
-        """Copy the group's curves ((flux, time) pairs) into pinned staging and
-        start one host-to-device copy per array on the copy stream."""
+        """Copy the group's curves ((flux, time) pairs) into pinned staging in
+        one native call and start one host-to-device copy per array on the
+        copy stream."""
         torch = self.torch
         n = sum(f.size for f, _ in parts)
         tok, tbuf, mem = self._pinned(self.ring_in, 12 * n)
-        # layout: time first (8-byte aligned), then flux
-        tview = mem[:8 * n].view(np.float64)
-        fview = mem[8 * n:12 * n].view(np.float32)
-        items, pos = [], 0
-        for f, t in parts:
-            items.append((pos, f, t))
-            pos += f.size
-
-        def copy(chunk):
-            for p0, f, t in chunk:
-                fview[p0:p0 + f.size] = f
-                tview[p0:p0 + f.size] = t
-        self._run_split(n, items, copy)
+        dst, src, nbytes, _ = staging_copies(parts, _addr(mem))
+        self._copy(dst, src, nbytes, self.copy_threads)
         with torch.cuda.stream(self.copy_stream):
             self.time[offset:offset + n].copy_(tbuf[:8 * n].view(torch.float64), non_blocking=True)
             self.flux[offset:offset + n].copy_(tbuf[8 * n:12 * n].view(torch.float32),
@@ -374,17 +361,12 @@ class GpuExecutor:
 
     def results(self, handle):
         handle[0].synchronize()
-        res = []
-        for tok, _, arr in handle[1]:
-            out = np.empty_like(arr)  # the ring block is reused right away
-            step = max(1, -(-arr.size // self.copy_threads))
-            pieces = [(a, arr[a:a + step]) for a in range(0, arr.size, step)]
-
-            def copy(chunk, out=out):
-                for a, src in chunk:
-                    out[a:a + src.size] = src
-            self._run_split(arr.size, pieces, copy)
-            res.append(out)
+        # fresh arrays: the ring blocks are reused right away
+        res = [np.empty_like(arr) for _, _, arr in handle[1]]
+        if res:
+            self._copy([_addr(o) for o in res], [_addr(arr) for _, _, arr in handle[1]],
+                       [o.nbytes for o in res], self.copy_threads)
+        for tok, _, _ in handle[1]:
             if tok is not None:
                 self.ring_out.release(tok)
         for tok in handle[2]:  # the step is done, so its uploads are too
@@ -394,8 +376,6 @@ class GpuExecutor:
 
     def close(self):
         self.plan.destroy()
-        if self._pool is not None:
-            self._pool.shutdown(wait=True)
 
 
 class FakeExecutor:

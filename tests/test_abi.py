@@ -236,3 +236,57 @@ def test_diag_library_exports_its_header():
     assert f(0, 8, ctypes.c_void_p(1), None, None) == 1
     assert f(10, 0, ctypes.c_void_p(1), None, None) == 1
     assert f(10, 8, None, None, None) == 1
+
+
+def test_serve_header_and_host_copy_many(lib):
+    """include/umi_serve.h: its symbol is exported, and the batched host copy
+    moves every byte of a ragged list (empty, sub-piece and multi-piece
+    copies, 1 and several threads, from two calling threads at once) and
+    rejects bad arguments before copying anything."""
+    import threading
+    text = open(os.path.join(ROOT, "include", "umi_serve.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(umi_[a-z_]+)\s*\(", text)))
+    assert names == ["umi_host_copy_many"]
+    for n in names:
+        assert hasattr(lib.lib, n), n
+    rng = np.random.default_rng(5)
+    sizes = [0, 1, 7, 1 << 20, (1 << 20) + 1, 3 * (1 << 20) + 12345, 100, 0, 5 << 20]
+    srcs = [rng.integers(0, 256, s, dtype=np.uint8) for s in sizes]
+    total = sum(sizes)
+
+    def one(threads):
+        dst = np.zeros(total, np.uint8)
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        lib.host_copy_many([dst.ctypes.data + int(o) for o in offs],
+                           [s.ctypes.data for s in srcs], sizes, threads)
+        assert np.array_equal(dst, np.concatenate(srcs))
+
+    for threads in [1, 2, 4, 8]:
+        one(threads)
+    errs = []
+
+    def hammer():
+        try:
+            for _ in range(20):
+                one(4)
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+    ts = [threading.Thread(target=hammer) for _ in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs
+    a = np.ones(8, np.uint8)
+    b = np.zeros(8, np.uint8)
+    lib.host_copy_many([], [], [], 4)  # n = 0: no-op
+    for bad in [dict(threads=0), dict(threads=65), dict(nbytes=[-1]), dict(dst=[0]),
+                dict(src=[0])]:
+        args = dict(dst=[b.ctypes.data], src=[a.ctypes.data], nbytes=[8], threads=2)
+        args.update(bad)
+        with pytest.raises(lib.UmiError):
+            lib.host_copy_many(args["dst"], args["src"], args["nbytes"], args["threads"])
+    assert not b.any()
+    f = lib.lib.umi_host_copy_many
+    assert f(None, None, None, 1, 1) == 1 and f(None, None, None, -1, 1) == 1

@@ -252,36 +252,28 @@ def test_pinned_ring_blocks_never_overlap(ops):
     assert ring.alloc(8192) is not None  # everything came back
 
 
-def test_split_copies_cover_every_sample_once():
-    """The executor's parallel staging copy: contiguous chunks over the copy
-    threads write every sample exactly once, in place."""
-    from concurrent.futures import ThreadPoolExecutor
-
-    from paper_2604_06602_amd.serve import GpuExecutor
-
-    class _E:
-        copy_threads = 4
-        PARALLEL_COPY_SAMPLES = 10
-        _pool = ThreadPoolExecutor(4)
-    run = GpuExecutor._run_split.__get__(_E())
+def test_staging_copies_lay_out_times_then_fluxes():
+    """The executor's staging copy list, run by the native batched copy into
+    an ordinary host buffer: every time array back to back, then every flux
+    array, each sample written once and nothing outside the staged bytes."""
+    from paper_2604_06602_amd import host_copy_many
+    from paper_2604_06602_amd.serve import staging_copies
     rng = np.random.default_rng(0)
     for trial in range(20):
-        parts = [rng.random(int(rng.integers(1, 60))).astype(np.float32)
-                 for _ in range(int(rng.integers(1, 40)))]
-        n = sum(p.size for p in parts)
-        dst = np.full(n, -1.0, np.float32)
-        items, pos = [], 0
-        for f in parts:
-            items.append((pos, f))
-            pos += f.size
-
-        def work(chunk):
-            for p0, f in chunk:
-                assert (dst[p0:p0 + f.size] == -1.0).all()  # nobody wrote here before
-                dst[p0:p0 + f.size] = f
-        run(n, items, work)
-        assert np.array_equal(dst, np.concatenate(parts))
-    _E._pool.shutdown()
+        parts = []
+        for _ in range(int(rng.integers(1, 40))):
+            L = int(rng.integers(0, 3000)) if trial % 5 else int(rng.integers(1, 400000))
+            parts.append((rng.random(L).astype(np.float32), rng.random(L) * 27.0))
+        n = sum(f.size for f, _ in parts)
+        buf = np.zeros(12 * n + 64, np.uint8)
+        dst, src, nbytes, got_n = staging_copies(parts, buf.ctypes.data)
+        assert got_n == n
+        host_copy_many(dst, src, nbytes, threads=1 + trial % 6)
+        t = buf[:8 * n].view(np.float64)
+        f = buf[8 * n:12 * n].view(np.float32)
+        assert np.array_equal(t, np.concatenate([p[1] for p in parts]))
+        assert np.array_equal(f, np.concatenate([p[0] for p in parts]))
+        assert not buf[12 * n:].any()
 
 
 def test_steps_respect_the_sample_limit_and_big_requests_still_run():
