@@ -79,7 +79,8 @@ def cpu_baseline(batch, budget_s: float = 15.0):
     import oracle
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    probe = max(8, int(cores))  # one curve per thread, so the probe sees the parallel rate
+    # one curve per thread, so the probe sees the parallel rate
+    probe = min(int(batch.n_curves), max(8, int(cores)))
     sub = batch_prefix(batch, probe)
     t0 = time.perf_counter()
     oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
@@ -219,8 +220,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", type=int, choices=[1, 2, 3], default=1,
-                    help="1: 1000x18k TESS batch, W=361 (headline); 2: 2000 Kepler-like curves "
+    ap.add_argument("--workload", type=int, choices=[0, 1, 2, 3], default=1,
+                    help="0: one 20k-sample TESS curve, W=361 (per-call latency); "
+                         "1: 1000x18k TESS batch, W=361 (headline); 2: 2000 Kepler-like curves "
                          "of 40k-70k, W=25; 3: 10,000 mixed curves of 1k-120k, W in "
                          "{25,121,361,721}, 5%% NaN gaps")
     ap.add_argument("--mode", choices=["persistent", "per-curve"], default="persistent")
@@ -368,7 +370,25 @@ def main(argv=None):
                      "steps": k, "speedup_of_%s" % args.mode: oms / ms_step}
         log("%s: %.3f ms per step" % (name, oms))
 
-    wl = {1: "tess_batch_1000x18k_w361", 2: "kepler_ragged_2000x40k-70k_w25",
+    latency = None
+    if args.workload == 0:
+        # one curve is launch-bound: time whole calls, launch to result on the device
+        # (host clock around the call and a stream synchronise)
+        walls = []
+        for _ in range(max(50, args.steps)):
+            w0 = time.perf_counter()
+            step()
+            stream.synchronize()
+            walls.append(time.perf_counter() - w0)
+        walls = np.array(walls) * 1e6
+        latency = {"call_to_done_us_p50": float(np.percentile(walls, 50)),
+                   "call_to_done_us_p99": float(np.percentile(walls, 99)),
+                   "device_us_per_call": ms_step * 1e3, "calls": int(walls.size)}
+        log("one curve: %.1f us device per call, %.1f us call to done (p50)"
+            % (ms_step * 1e3, latency["call_to_done_us_p50"]))
+
+    wl = {0: "tess_single_20k_w361", 1: "tess_batch_1000x18k_w361",
+          2: "kepler_ragged_2000x40k-70k_w25",
           3: "mixed_ragged_10000x1k-120k_wmix"}[args.workload]
     out = {
         "metric": METRIC if args.workload == 1 else "window-estimates/s (%s)" % wl,
@@ -400,6 +420,8 @@ def main(argv=None):
     }
     if per_curve is not None:
         out["comparison"] = per_curve
+    if latency is not None:
+        out["latency"] = latency
     if args.workload != 1:
         out["roofline"]["traffic"] = None  # the committed counters cover workload 1 only
     if not args.no_serve_leg:

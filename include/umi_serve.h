@@ -6,8 +6,9 @@
  * flux and time into pinned host memory before one host-to-device copy, and
  * copies each result back out of pinned memory afterwards.  Done curve by
  * curve from an interpreter, those copies cost more in per-call overhead and
- * lock hand-offs than in bytes moved; this entry point does a whole list of
- * them in one call, split over a small pool of native threads.
+ * lock hand-offs than in bytes moved; these entry points do a whole list of
+ * them in one call: host-to-host copies split over a small pool of native
+ * threads, and host/device copies enqueued on a stream.
  */
 #ifndef UMI_SERVE_H
 #define UMI_SERVE_H
@@ -36,6 +37,25 @@ extern "C" {
  * UMI_ERR_INVALID_ARG before anything is copied.  n = 0 is a no-op. */
 umi_status umi_host_copy_many(void* const* dst, const void* const* src, const int64_t* bytes,
                               int64_t n, int32_t threads);
+
+#define UMI_COPY_H2D 1
+#define UMI_COPY_D2H 2
+
+/* Asynchronous host/device copies on `stream` (a hipStream_t, NULL = the
+ * legacy default stream): for i in [0, n), bytes[i] bytes from src[i] to
+ * dst[i], host to device when kind is UMI_COPY_H2D and device to host when it
+ * is UMI_COPY_D2H, enqueued in order.  The three arrays are [host] and read
+ * before the call returns; the host side of each copy should be pinned memory
+ * (hipHostMalloc), or the runtime may complete the copy before returning.  The
+ * caller keeps every buffer alive, and the host buffers untouched, until the
+ * stream work completes.  For the serving loop: the copies of a whole step in
+ * one call.
+ * Errors: n < 0, an unknown kind, a NULL array with n > 0, a negative size or
+ * a NULL pointer with a positive size give UMI_ERR_INVALID_ARG before anything
+ * is enqueued; a failing enqueue gives UMI_ERR_DEVICE (copies before it stay
+ * enqueued).  n = 0 is a no-op. */
+umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_t* bytes,
+                          int64_t n, int32_t kind, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,9 @@ from ._lib import (  # noqa: F401
     detrend_batch_into,
     detrend_gather_into,
     host_copy_many,
+    copy_async,
+    COPY_H2D,
+    COPY_D2H,
     last_error,
     release,
     set_tuning,

@@ -62,7 +62,7 @@ def _load():
     # Loaded the other way round a process would hold two HIP runtimes.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libumi.so is not built (%s); run `python -m paper_2604_06602_amd.build` "
+        raise ImportError("libumi.so is not built (%s); run `python paper_2604_06602_amd/build.py` "
                           "or __graft_entry__.build()" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     lib.umi_detrend.restype = ctypes.c_int
@@ -106,6 +106,8 @@ def _load():
     lib.umi_debug_inject_error.argtypes = [ctypes.c_int]
     lib.umi_host_copy_many.restype = ctypes.c_int
     lib.umi_host_copy_many.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32]
+    lib.umi_copy_async.restype = ctypes.c_int
+    lib.umi_copy_async.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
     return lib
 
 
@@ -128,6 +130,22 @@ def host_copy_many(dst_ptrs, src_ptrs, nbytes, threads: int = 1):
         raise ValueError("host_copy_many: three 1-D arrays of equal length")
     _check(lib.umi_host_copy_many(d.ctypes.data, s.ctypes.data, b.ctypes.data, b.size,
                                   int(threads)))
+
+
+COPY_H2D, COPY_D2H = 1, 2
+
+
+def copy_async(dst_ptrs, src_ptrs, nbytes, kind: int, stream=None):
+    """Enqueue host<->device copies (kind COPY_H2D or COPY_D2H) of nbytes[i]
+    from src_ptrs[i] to dst_ptrs[i] on `stream` (a torch stream, a raw
+    hipStream_t address, or None for the current stream) in one native call."""
+    d = np.ascontiguousarray(dst_ptrs, np.uint64)
+    s = np.ascontiguousarray(src_ptrs, np.uint64)
+    b = np.ascontiguousarray(nbytes, np.int64)
+    if not (d.shape == s.shape == b.shape and b.ndim == 1):
+        raise ValueError("copy_async: three 1-D arrays of equal length")
+    st = ctypes.c_void_p(stream) if isinstance(stream, int) else _stream_handle(stream)
+    _check(lib.umi_copy_async(d.ctypes.data, s.ctypes.data, b.ctypes.data, b.size, int(kind), st))
 
 
 def last_error() -> str:

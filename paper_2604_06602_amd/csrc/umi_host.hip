@@ -939,4 +939,27 @@ umi_status umi_host_copy_many(void* const* dst, const void* const* src, const in
     return UMI_OK;
 }
 
+umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_t* bytes,
+                          int64_t n, int32_t kind, void* stream)
+{
+    if (n < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: n < 0");
+    if (kind != UMI_COPY_H2D && kind != UMI_COPY_D2H)
+        return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: unknown kind");
+    if (n == 0) return UMI_OK;
+    if (!dst || !src || !bytes) return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: NULL array");
+    for (int64_t i = 0; i < n; ++i) {
+        if (bytes[i] < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: bytes < 0");
+        if (bytes[i] > 0 && (!dst[i] || !src[i]))
+            return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: NULL pointer");
+    }
+    const hipMemcpyKind k = kind == UMI_COPY_H2D ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    for (int64_t i = 0; i < n; ++i) {
+        if (bytes[i] == 0) continue;
+        const hipError_t e = hipMemcpyAsync(dst[i], src[i], size_t(bytes[i]), k,
+                                            static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return umi::fail_hip(e, "umi_copy_async: hipMemcpyAsync");
+    }
+    return UMI_OK;
+}
+
 }  // extern "C"

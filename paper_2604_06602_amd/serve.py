@@ -293,10 +293,20 @@ class GpuExecutor:
         self.max_W = int(max_W)
         self.ring_in = PinnedRing(torch, staging_bytes)        # flux + time of admitted groups
         self.ring_out = PinnedRing(torch, staging_bytes // 3)  # trend of finished steps
-        # native threads for the copies into and out of pinned staging
+        # native threads for the copies into and out of pinned staging; the
+        # host<->device copies of a group or a step are one native call each
         self.copy_threads = max(1, int(copy_threads))
         self._copy = _lib.host_copy_many
+        self._copy_async = _lib.copy_async
+        self._H2D, self._D2H = _lib.COPY_H2D, _lib.COPY_D2H
+        self._flux_ptr = self.flux.data_ptr()
+        self._time_ptr = self.time.data_ptr()
+        self._trend_ptr = self.trend.data_ptr()
+        self._copy_stream_ptr = int(self.copy_stream.cuda_stream)
         self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
+        # seconds spent in each part of staging and launching (diagnostics)
+        self.phase_s = {"stage_alloc": 0.0, "stage_list": 0.0, "stage_copy": 0.0,
+                        "h2d": 0.0, "launch_plan": 0.0, "d2h": 0.0, "results": 0.0}
 
     def _pinned(self, ring, nbytes):
         got = ring.alloc(nbytes)
@@ -313,15 +323,27 @@ class GpuExecutor:
         copy stream."""
         torch = self.torch
         n = sum(f.size for f, _ in parts)
+        if not (0 <= offset and offset + n <= self.capacity):
+            raise ValueError("upload range [%d, %d) outside the arena" % (offset, offset + n))
+        clk = _time.perf_counter
+        ph = self.phase_s
+        t0 = clk()
         tok, tbuf, mem = self._pinned(self.ring_in, 12 * n)
-        dst, src, nbytes, _ = staging_copies(parts, _addr(mem))
+        base = _addr(mem)
+        t1 = clk()
+        dst, src, nbytes, _ = staging_copies(parts, base)
+        t2 = clk()
         self._copy(dst, src, nbytes, self.copy_threads)
-        with torch.cuda.stream(self.copy_stream):
-            self.time[offset:offset + n].copy_(tbuf[:8 * n].view(torch.float64), non_blocking=True)
-            self.flux[offset:offset + n].copy_(tbuf[8 * n:12 * n].view(torch.float32),
-                                               non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.copy_stream)
+        t3 = clk()
+        self._copy_async([self._time_ptr + 8 * offset, self._flux_ptr + 4 * offset],
+                         [base, base + 8 * n], [8 * n, 4 * n], self._H2D, self._copy_stream_ptr)
+        ev = torch.cuda.Event()
+        ev.record(self.copy_stream)
+        t4 = clk()
+        ph["stage_alloc"] += t1 - t0
+        ph["stage_list"] += t2 - t1
+        ph["stage_copy"] += t3 - t2
+        ph["h2d"] += t4 - t3
         return (ev, tok, tbuf)
 
     def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
@@ -330,6 +352,10 @@ class GpuExecutor:
     def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
         """Run one batch; then copy each (offset, size) range of the trend back."""
         torch = self.torch
+        for off, size in ranges:
+            if not (0 <= off and off + size <= self.capacity):
+                raise ValueError("result range [%d, %d) outside the arena" % (off, off + size))
+        t0 = _time.perf_counter()
         for ev, _, _ in uploads:
             self.compute_stream.wait_event(ev)
         try:
@@ -344,22 +370,28 @@ class GpuExecutor:
             raise
         computed = torch.cuda.Event()
         computed.record(self.compute_stream)
-        outs = []
-        with torch.cuda.stream(self.copy_stream):
-            self.copy_stream.wait_event(computed)
-            for off, size in ranges:
-                tok, tbuf, mem = self._pinned(self.ring_out, 4 * size)
-                tbuf[:4 * size].view(torch.float32).copy_(self.trend[off:off + size],
-                                                          non_blocking=True)
-                outs.append((tok, tbuf, mem[:4 * size].view(np.float32)))
-            done = torch.cuda.Event()
-            done.record(self.copy_stream)
+        t1 = _time.perf_counter()
+        self.copy_stream.wait_event(computed)
+        outs, dst, src, nbytes = [], [], [], []
+        for off, size in ranges:
+            tok, tbuf, mem = self._pinned(self.ring_out, 4 * size)
+            arr = mem[:4 * size].view(np.float32)
+            outs.append((tok, tbuf, arr))
+            dst.append(_addr(arr))
+            src.append(self._trend_ptr + 4 * off)
+            nbytes.append(4 * size)
+        self._copy_async(dst, src, nbytes, self._D2H, self._copy_stream_ptr)
+        done = torch.cuda.Event()
+        done.record(self.copy_stream)
+        self.phase_s["launch_plan"] += t1 - t0
+        self.phase_s["d2h"] += _time.perf_counter() - t1
         return (done, outs, [u[1] for u in uploads])
 
     def ready(self, handle) -> bool:
         return handle[0].query()
 
     def results(self, handle):
+        t0 = _time.perf_counter()
         handle[0].synchronize()
         # fresh arrays: the ring blocks are reused right away
         res = [np.empty_like(arr) for _, _, arr in handle[1]]
@@ -372,6 +404,7 @@ class GpuExecutor:
         for tok in handle[2]:  # the step is done, so its uploads are too
             if tok is not None:
                 self.ring_in.release(tok)
+        self.phase_s["results"] += _time.perf_counter() - t0
         return res
 
     def close(self):
@@ -505,12 +538,19 @@ class Server:
         with self._lock:
             out = self.stats.summary(self.arena)
             out["pinned_fallbacks"] = getattr(self.ex, "pinned_fallbacks", None)
+            ph = getattr(self.ex, "phase_s", None)
+            if ph is not None:
+                out["executor_phase_s"] = dict(ph)
             return out
 
     def reset_stats(self):
         """Start a new measurement window (e.g. after a warm-up)."""
         with self._lock:
             self.stats = Stats()
+            ph = getattr(self.ex, "phase_s", None)
+            if ph is not None:
+                for k in ph:
+                    ph[k] = 0.0
             self.arena.high_water = self.arena.used
 
     # -- scheduler ---------------------------------------------------------

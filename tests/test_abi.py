@@ -247,7 +247,7 @@ def test_serve_header_and_host_copy_many(lib):
     text = open(os.path.join(ROOT, "include", "umi_serve.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = sorted(set(re.findall(r"\b(umi_[a-z_]+)\s*\(", text)))
-    assert names == ["umi_host_copy_many"]
+    assert names == ["umi_copy_async", "umi_host_copy_many"]
     for n in names:
         assert hasattr(lib.lib, n), n
     rng = np.random.default_rng(5)
@@ -290,3 +290,17 @@ def test_serve_header_and_host_copy_many(lib):
     assert not b.any()
     f = lib.lib.umi_host_copy_many
     assert f(None, None, None, 1, 1) == 1 and f(None, None, None, -1, 1) == 1
+
+
+def test_copy_async_rejects_bad_arguments(lib):
+    """umi_copy_async checks everything before enqueueing (no device call is
+    made here: every case fails validation, and n = 0 is a no-op)."""
+    a = np.ones(8, np.uint8)
+    lib.copy_async([], [], [], lib.COPY_H2D, 0)
+    for bad in [dict(kind=0), dict(kind=3), dict(nbytes=[-1]), dict(dst=[0]), dict(src=[0])]:
+        args = dict(dst=[a.ctypes.data], src=[a.ctypes.data], nbytes=[8], kind=lib.COPY_D2H)
+        args.update(bad)
+        with pytest.raises(lib.UmiError):
+            lib.copy_async(args["dst"], args["src"], args["nbytes"], args["kind"], 0)
+    f = lib.lib.umi_copy_async
+    assert f(None, None, None, 1, 1, None) == 1 and f(None, None, None, -1, 1, None) == 1

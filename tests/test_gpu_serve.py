@@ -62,3 +62,27 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
         assert np.array_equal(np.isnan(res[idx]), ~ok)
         rel = np.abs(res[idx][ok] - o_tr[ok]) / np.abs(o_tr[ok])
         assert rel.max() <= 1e-5
+
+
+def test_copy_async_round_trip(torch):
+    """The serving loop's batched host<->device copies: a ragged list of
+    pinned-host ranges up to the device and back on one stream, every byte
+    where it belongs and nothing written past the ranges."""
+    import paper_2604_06602_amd as umi
+    rng = np.random.default_rng(9)
+    sizes = [0, 1, 4096, 1 << 20, 3 * (1 << 20) + 5]
+    total = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    host = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+    host.numpy()[:] = rng.integers(0, 256, total, dtype=np.uint8)
+    back = torch.zeros(total, dtype=torch.uint8, pin_memory=True)
+    dev = torch.zeros(total + 64, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    umi.copy_async([dev.data_ptr() + int(o) for o in offs], [host.data_ptr() + int(o) for o in offs],
+                   sizes, umi.COPY_H2D, s)
+    umi.copy_async([back.data_ptr() + int(o) for o in offs], [dev.data_ptr() + int(o) for o in offs],
+                   sizes, umi.COPY_D2H, s)
+    s.synchronize()
+    assert torch.equal(back, host)
+    assert not dev[total:].any().item()
