@@ -666,6 +666,7 @@ class Server:
 
     def _loop(self):
         clk = self.clock
+        groups = []
         try:
             while True:
                 t0 = clk()
@@ -716,10 +717,22 @@ class Server:
         except BaseException as e:  # keep the failure visible to close()
             self._error = e
             with self._lock:
-                for r in list(self._waiting):
-                    if not r.future.done():
-                        r.future.set_exception(RuntimeError("scheduler failed: %r" % e))
-                self._waiting.clear()
+                self._fail_all(RuntimeError("scheduler failed: %r" % e), groups)
+
+    def _fail_all(self, err, in_hand=()):
+        """Fail every request not yet resolved: waiting, admitted (queued for
+        upload, in the groups being uploaded, uploaded) and in flight.  Called
+        with the lock held."""
+        reqs = list(self._waiting)
+        for g in list(self._to_upload) + list(in_hand) + list(self._groups):
+            reqs.extend(g.requests)
+        for st in self._inflight:
+            for g in st.groups:
+                reqs.extend(g.requests)
+        for r in reqs:
+            if not r.future.done():
+                r.future.set_exception(err)
+        self._waiting.clear()
 
 
 # ---------------------------------------------------------------------------

@@ -295,3 +295,23 @@ def test_steps_respect_the_sample_limit_and_big_requests_still_run():
     assert 2500 in seen
     assert all(s <= 1000 for s in seen if s != 2500)
     assert sum(seen) == 30 * 300 + 2500
+
+
+def test_upload_failure_fails_every_request_and_close_reports_it():
+    """An exception in the uploader thread stops serving: every request ever
+    submitted resolves (none hangs), those not finished with an error, and
+    close() reports the failure."""
+    class Failing(FakeExecutor):
+        n = 0
+
+        def upload(self, offset, flux, time):
+            Failing.n += 1
+            if Failing.n == 3:
+                raise OSError("staging failed")
+            return super().upload(offset, flux, time)
+    srv = Server(Failing(100000, delay=0.002), max_step_curves=2)
+    futs = [srv.submit(np.ones(100, np.float32), W=5) for _ in range(12)]
+    done = [fu.exception(timeout=10) is None for fu in futs]
+    assert not all(done) and any(isinstance(fu.exception(), RuntimeError) for fu in futs)
+    with pytest.raises(RuntimeError):
+        srv.close(timeout=10)
