@@ -200,8 +200,13 @@ struct Packed {
     int gpc = kDefaultGroupsPerCU;      // persistent groups per CU
 };
 
+// Tile sizes a batch too small to give every CU a tile falls back to, largest
+// first: at 512 each lane of a workgroup takes one window.
+constexpr int kSmallBatchTiles[] = {1024, 512};
+
 umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
-                float alpha, float c, const umi_options& o, const umi_launch& opt, Packed* out)
+                float alpha, float c, const umi_options& o, const umi_launch& opt, int n_cu,
+                int64_t max_tiles, Packed* out)
 {
     std::vector<int> tile_of((size_t)n);
     std::vector<int32_t> order;
@@ -212,6 +217,25 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
         if (opt.tile > 0) t = std::min(opt.tile, max_tile(W[b]));
         tile_of[(size_t)b] = t;
         if (lengths[b] > 0) order.push_back((int32_t)b);
+    }
+    // A batch that the tuned tiles cut into fewer tiles than there are CUs
+    // (one curve, a quiet serving step) would leave most of the chip idle:
+    // smaller tiles spread its windows over more CUs.  Results do not depend
+    // on the tiling.  An explicit launch tile is kept as given.
+    auto count_tiles = [&](int cap) {
+        int64_t t = 0;
+        for (int32_t b : order) {
+            const int tb = cap > 0 ? std::min(tile_of[(size_t)b], cap) : tile_of[(size_t)b];
+            t += (lengths[b] + tb - 1) / tb;
+        }
+        return t;
+    };
+    if (opt.tile == 0 && count_tiles(0) < n_cu) {
+        for (int cap : kSmallBatchTiles) {
+            if (count_tiles(cap) > max_tiles) break;
+            for (int32_t b : order) tile_of[(size_t)b] = std::min(tile_of[(size_t)b], cap);
+            if (count_tiles(0) >= n_cu) break;
+        }
     }
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         const int64_t ca = (int64_t)W[a] * tile_of[(size_t)a];
@@ -467,13 +491,14 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     if (total == 0) return UMI_OK;
     if (!flux || !trend) return fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
 
-    Packed p;
-    if ((st = pack(offsets, lengths, n_curves, W, alpha, c, o, opt, &p)) != UMI_OK) return st;
-    const int64_t nc = (int64_t)p.curves.size();
-
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    Packed p;
+    if ((st = pack(offsets, lengths, n_curves, W, alpha, c, o, opt, cu_count(device),
+                   (int64_t)INT32_MAX, &p)) != UMI_OK)
+        return st;
+    const int64_t nc = (int64_t)p.curves.size();
     Workspace* ws = workspace_for(device, stream);
     std::lock_guard<std::mutex> lk(ws->mu);
     if ((e = ws->reserve(span, nc, p.ntiles)) != hipSuccess)
@@ -783,7 +808,8 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
     const umi_launch opt = {UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
     umi::Packed pk;
     if (n_curves > 0 &&
-        (st = umi::pack(offsets, lengths, n_curves, W, alpha, c, o, opt, &pk)) != UMI_OK)
+        (st = umi::pack(offsets, lengths, n_curves, W, alpha, c, o, opt,
+                        umi::cu_count(p->device), p->max_tiles, &pk)) != UMI_OK)
         return st;
     if (pk.ntiles > p->max_tiles)
         return umi::fail(UMI_ERR_UNSUPPORTED, "batch needs more tiles than the plan holds");

@@ -253,16 +253,13 @@ def test_small_window_network_path(torch, umi, oracle_lib):
     for a, c in [(2.0, 5.0), (10.0, 2.5)]:
         o_tr, o_md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W,
                                               alpha=a, c=c)
-        # default tiles (three windows per lane), then tiles whose last lanes
-        # hold two, and tiles of two and of one window per lane
-        for table in [None, "31 1100 4", "31 700 4", "31 300 4"]:
-            umi.set_tuning(table)
-            try:
-                g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths,
-                                       packed.W, alpha=a, c=c)
-            finally:
-                umi.set_tuning(None)
-            assert_parity(g_tr, g_md, o_tr, o_md, what="small W a=%g tiles %s" % (a, table),
+        # tiles of three windows per lane, then tiles whose last lanes hold
+        # two, and tiles of two and of one window per lane (explicit launch
+        # tiles), and the library's own choice for a batch this small
+        for tile in [1536, 1100, 700, 300, 0]:
+            g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths,
+                                   packed.W, launch=umi.LaunchOptions(tile=tile), alpha=a, c=c)
+            assert_parity(g_tr, g_md, o_tr, o_md, what="small W a=%g tile %d" % (a, tile),
                           scale=mag)
 
 
