@@ -91,11 +91,12 @@ def cpu_baseline(batch, budget_s: float = 15.0):
     tr, _ = oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
     dt = time.perf_counter() - t0
     windows = int(np.isfinite(tr).sum())
-    return {"value": windows / dt, "unit": "window-estimates/s", "cores": int(cores),
+    used = min(int(cores), n)  # the oracle runs one curve per thread
+    return {"value": windows / dt, "unit": "window-estimates/s", "cores": used,
             "kind": "oracle", "cpu": cpu_model(),
-            "per_core": windows / dt / max(1, int(cores)),
+            "per_core": windows / dt / max(1, used),
             "sample": "first %d of the %d curves (%d windows), FP64 C oracle, %d threads, %.1f s"
-                      % (n, batch.n_curves, windows, cores, dt)}
+                      % (n, batch.n_curves, windows, used, dt)}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "umi_main_kernel__tess_batch_1000x18k_w361.md")
