@@ -565,11 +565,15 @@ class CopyPool {
         std::lock_guard<std::mutex> one_at_a_time(call_mu_);
         {
             std::lock_guard<std::mutex> lk(mu_);
-            while ((int)workers_ < threads - 1) {
-                std::thread(&CopyPool::worker, this).detach();
-                ++workers_;
+            try {
+                while ((int)workers_ < threads - 1) {
+                    std::thread(&CopyPool::worker, this).detach();
+                    ++workers_;
+                }
+            } catch (...) {
+                // no more threads: the ones there are (and the caller) do the job
             }
-            job.slots = threads - 1;
+            job.slots = std::min(threads - 1, (int)workers_);
             job_ = &job;
             ++gen_;
         }
