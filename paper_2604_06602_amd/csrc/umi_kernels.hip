@@ -559,9 +559,14 @@ __device__ __forceinline__ void sort32(uint32_t (&k)[32])
 // The points strictly above each median are counted on the unsorted keys.
 // Keys past kp[lim] are never read.  Same results as the tile-sort path,
 // without the tile sort and wavelet matrix.
-__device__ __forceinline__ void small_window_medians(const uint32_t* __restrict__ kp, int W,
+// kW > 0 fixes W at compile time: the padding and the median rank are then
+// constants, and the compiler drops every comparator that only moves padding
+// or feeds ranks other than q-2 .. q.
+template <int kW>
+__device__ __forceinline__ void small_window_medians(const uint32_t* __restrict__ kp, int W_rt,
                                                      int nwin, int lim, float* pm, uint32_t* pn)
 {
+    const int W = kW > 0 ? kW : W_rt;
     const int q = (W - 1) >> 1;  // <= 15, the same for the whole tile
     uint32_t med[3];
     if (W == 1) {
@@ -897,7 +902,10 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             const int p0 = t0 + tid * R;
             if (p0 < t1) {
                 const int b = p0 - h - s0;
-                small_window_medians(keys + b, cd.W, min(R, t1 - p0), N - 1 - b, pm, pn);
+                if (cd.W == 25)  // the Kepler long-cadence window
+                    small_window_medians<25>(keys + b, 25, min(R, t1 - p0), N - 1 - b, pm, pn);
+                else
+                    small_window_medians<0>(keys + b, cd.W, min(R, t1 - p0), N - 1 - b, pm, pn);
             }
         }
         if (R == 3)
