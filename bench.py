@@ -249,9 +249,9 @@ def main(argv=None):
                          "HBM byte counters) and exit")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU: the estimate shards over curves with no exchange, "
-              "and this build runs on a single MI355X; --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
+        print("bench.py measures one GPU: the estimate would shard over curves with no "
+              "exchange step, but only single-GPU runs are implemented; --gpus %d is not "
+              "supported" % args.gpus, file=sys.stderr)
         return 2
 
     import torch

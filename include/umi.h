@@ -60,7 +60,7 @@ typedef enum {
     UMI_ERR_INVALID_ARG = 1, /* bad argument; nothing enqueued */
     UMI_ERR_NO_MEMORY = 2,   /* workspace could not be allocated */
     UMI_ERR_DEVICE = 3,      /* a HIP runtime or launch error */
-    UMI_ERR_UNSUPPORTED = 4  /* valid but outside this build's limits (W) */
+    UMI_ERR_UNSUPPORTED = 4  /* valid but outside the library's limits (W) */
 } umi_status;
 
 /* Launch modes of the batch call. */
