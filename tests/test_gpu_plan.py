@@ -148,3 +148,29 @@ def test_plan_rejects_oversized_batches(torch, umi):
     s.synchronize()
     assert np.isfinite(trend[:3000].cpu().numpy()).all()
     plan.destroy()
+
+
+def test_plan_small_batch_tiles_stay_within_its_capacity(torch, umi):
+    """A plan sized for exactly one 20,000-sample curve: the small-batch tile
+    rule may not cut that curve into more tiles than the plan holds, and the
+    replay equals the direct call (whose tiles the rule does cut) bit for
+    bit, on the first replay and after eager work on the second."""
+    f, t, W = synth.curve_config0()
+    cap = f.size
+    flux = torch.from_numpy(f).cuda()
+    time = torch.from_numpy(t).cuda()
+    trend = torch.empty_like(flux)
+    s = torch.cuda.Stream()
+    plan = umi.Plan(flux, time, trend, None, max_curves=1, max_W=W, stream=s)
+    ref, _ = umi.detrend(flux, time, W)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    for rep in range(2):
+        trend.fill_(7.0)
+        torch.cuda.synchronize()
+        plan.run([0], [cap], [W])
+        s.synchronize()
+        assert np.array_equal(trend.cpu().numpy().view(np.uint32), ref.view(np.uint32)), rep
+        umi.detrend(flux, time, W)  # eager work between the replays
+        torch.cuda.synchronize()
+    plan.destroy()
