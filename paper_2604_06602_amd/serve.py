@@ -7,7 +7,9 @@ A scheduler thread
     device-memory budget: the budget is one resident arena of device arrays
     (flux, time, trend) plus the plan's per-sample workspace, and every
     admission group (the requests admitted together) gets one contiguous
-    range of it, filled by a single host-to-device copy on a copy stream;
+    range of it: its curves are staged into a pinned ring by one batched
+    native copy, then uploaded with one host-to-device copy per array on a
+    copy stream;
   * launches steps: all admitted, not yet launched groups that share the
     iteration count go into one batch -- each curve keeps its own alpha and
     c (the Table 4 settings mix freely) -- run through a replayable plan (a
@@ -16,8 +18,9 @@ A scheduler thread
     are in flight, so requests that arrive while one step runs are uploaded
     and staged concurrently and run in the next step;
   * completes steps: the trend of each group comes back with one
-    device-to-host copy, requests are resolved, and their arena ranges and
-    budget are released.
+    device-to-host copy into the pinned ring and one batched native copy
+    out of it, requests are resolved, and their arena ranges and budget are
+    released.
 
 Latency is measured from the request's arrival time (``submit``'s
 ``arrival`` argument, defaulting to now: an open-loop driver passes the
