@@ -31,6 +31,7 @@ with ``FakeExecutor``.
 """
 from __future__ import annotations
 
+import bisect
 import itertools
 import threading
 import time as _time
@@ -221,6 +222,24 @@ def staging_copies(parts, base: int):
     return dst, src, nbytes, n
 
 
+class PinnedRegistry:
+    """Host address ranges known to be pinned (page-locked) memory, so that
+    an array inside one can be the source of an asynchronous upload."""
+
+    def __init__(self):
+        self._starts: list = []
+        self._ends: list = []
+
+    def add(self, start: int, nbytes: int):
+        i = bisect.bisect_left(self._starts, start)
+        self._starts.insert(i, int(start))
+        self._ends.insert(i, int(start) + int(nbytes))
+
+    def covers(self, start: int, nbytes: int) -> bool:
+        i = bisect.bisect_right(self._starts, start) - 1
+        return i >= 0 and start + nbytes <= self._ends[i]
+
+
 class PinnedRing:
     """A preallocated pinned host buffer handed out as a ring: blocks are
     allocated at the head and released in any order; space comes back when
@@ -307,6 +326,9 @@ class GpuExecutor:
         self._trend_ptr = self.trend.data_ptr()
         self._copy_stream_ptr = int(self.copy_stream.cuda_stream)
         self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
+        self._registry = PinnedRegistry()  # client arrays from pinned_empty()
+        self._client_pinned: list = []
+        self.direct_uploads = 0    # groups uploaded straight from client memory
         # seconds spent in each part of staging and launching (diagnostics)
         self.phase_s = {"stage_alloc": 0.0, "stage_list": 0.0, "stage_copy": 0.0,
                         "h2d": 0.0, "launch_plan": 0.0, "d2h": 0.0, "results": 0.0}
@@ -320,14 +342,77 @@ class GpuExecutor:
         tok, start = got
         return tok, ring.buf[start:start + int(nbytes)], ring.mem[start:start + int(nbytes)]
 
+    def pinned_empty(self, n: int, dtype) -> np.ndarray:
+        """A host array in pinned memory, kept for the executor's lifetime.
+        A group whose requests all hold their flux and time in such arrays is
+        uploaded straight from them, without the staging copy; the caller
+        leaves those arrays unchanged until the request's result arrives."""
+        dt = np.dtype(dtype)
+        t = self.torch.empty(max(1, int(n)) * dt.itemsize, dtype=self.torch.uint8,
+                             pin_memory=True)
+        self._client_pinned.append(t)
+        arr = t.numpy().view(dt)[:int(n)]
+        self._registry.add(_addr(arr), arr.nbytes)
+        return arr
+
+    def _direct_copies(self, offset: int, parts):
+        """(dst, src, nbytes) of the host-to-device copies that upload a group
+        straight from its requests' pinned arrays."""
+        k = len(parts)
+        sizes = np.fromiter((f.size for f, _ in parts), np.int64, k)
+        pos = np.zeros(k, np.int64)
+        np.cumsum(sizes[:-1], out=pos[1:])
+        dst = np.concatenate([self._time_ptr + 8 * (offset + pos),
+                              self._flux_ptr + 4 * (offset + pos)]).astype(np.uint64)
+        src = np.fromiter(itertools.chain((_addr(t) for _, t in parts),
+                                          (_addr(f) for f, _ in parts)), np.uint64, 2 * k)
+        return dst, src, np.concatenate([8 * sizes, 4 * sizes])
+
+    def _is_direct(self, parts) -> bool:
+        reg = self._registry
+        return all(reg.covers(_addr(f), f.nbytes) and reg.covers(_addr(t), t.nbytes)
+                   for f, t in parts)
+
+    def upload_many(self, groups):
+        """Upload several groups ((offset, parts) pairs): those held wholly in
+        pinned client memory with one native call and one event between them,
+        the rest through staging.  Returns one upload handle per group."""
+        out = [None] * len(groups)
+        direct = []
+        for i, (offset, parts) in enumerate(groups):
+            n = sum(f.size for f, _ in parts)
+            if not (0 <= offset and offset + n <= self.capacity):
+                raise ValueError("upload range [%d, %d) outside the arena" % (offset, offset + n))
+            if self._is_direct(parts):
+                direct.append(i)
+            else:
+                out[i] = self.stage_upload(offset, parts)
+        if direct:
+            t0 = _time.perf_counter()
+            cps = [self._direct_copies(*groups[i]) for i in direct]
+            self._copy_async(np.concatenate([c[0] for c in cps]),
+                             np.concatenate([c[1] for c in cps]),
+                             np.concatenate([c[2] for c in cps]), self._H2D,
+                             self._copy_stream_ptr)
+            ev = self.torch.cuda.Event()
+            ev.record(self.copy_stream)
+            for i in direct:
+                out[i] = (ev, None, None)
+            self.direct_uploads += len(direct)
+            self.phase_s["h2d"] += _time.perf_counter() - t0
+        return out
+
     def stage_upload(self, offset: int, parts):
         """Copy the group's curves ((flux, time) pairs) into pinned staging in
         one native call and start one host-to-device copy per array on the
-        copy stream."""
+        copy stream -- or, when every array is in memory from pinned_empty(),
+        upload straight from it."""
         torch = self.torch
         n = sum(f.size for f, _ in parts)
         if not (0 <= offset and offset + n <= self.capacity):
             raise ValueError("upload range [%d, %d) outside the arena" % (offset, offset + n))
+        if self._is_direct(parts):
+            return self.upload_many([(offset, parts)])[0]
         clk = _time.perf_counter
         ph = self.phase_s
         t0 = clk()
@@ -359,8 +444,11 @@ class GpuExecutor:
             if not (0 <= off and off + size <= self.capacity):
                 raise ValueError("result range [%d, %d) outside the arena" % (off, off + size))
         t0 = _time.perf_counter()
-        for ev, _, _ in uploads:
-            self.compute_stream.wait_event(ev)
+        seen = set()
+        for ev, _, _ in uploads:  # groups uploaded together share one event
+            if id(ev) not in seen:
+                seen.add(id(ev))
+                self.compute_stream.wait_event(ev)
         try:
             self.plan.run(offsets, lengths, Ws, np.asarray(alphas, np.float32),
                           np.asarray(cs, np.float32), iters)
@@ -541,6 +629,7 @@ class Server:
         with self._lock:
             out = self.stats.summary(self.arena)
             out["pinned_fallbacks"] = getattr(self.ex, "pinned_fallbacks", None)
+            out["direct_uploads"] = getattr(self.ex, "direct_uploads", None)
             ph = getattr(self.ex, "phase_s", None)
             if ph is not None:
                 out["executor_phase_s"] = dict(ph)
@@ -554,6 +643,8 @@ class Server:
             if ph is not None:
                 for k in ph:
                     ph[k] = 0.0
+            if hasattr(self.ex, "direct_uploads"):
+                self.ex.direct_uploads = 0
             self.arena.high_water = self.arena.used
 
     # -- scheduler ---------------------------------------------------------
@@ -587,6 +678,12 @@ class Server:
         return groups
 
     def _upload(self, groups):
+        if hasattr(self.ex, "upload_many"):
+            ups = self.ex.upload_many([(g.offset, [(r.flux, r.time) for r in g.requests])
+                                       for g in groups])
+            for g, up in zip(groups, ups):
+                g.upload = up
+            return
         for g in groups:
             parts = [(r.flux, r.time) for r in g.requests]
             if hasattr(self.ex, "stage_upload"):

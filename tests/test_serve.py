@@ -315,3 +315,21 @@ def test_upload_failure_fails_every_request_and_close_reports_it():
     assert not all(done) and any(isinstance(fu.exception(), RuntimeError) for fu in futs)
     with pytest.raises(RuntimeError):
         srv.close(timeout=10)
+
+
+def test_pinned_registry_covers_only_whole_ranges():
+    """The executor uploads straight from a client array only if the array
+    lies wholly inside one registered pinned range."""
+    from paper_2604_06602_amd.serve import PinnedRegistry
+    reg = PinnedRegistry()
+    reg.add(1000, 100)
+    reg.add(5000, 10)
+    reg.add(2000, 500)
+    assert reg.covers(1000, 100) and reg.covers(1050, 50) and reg.covers(2100, 400)
+    assert reg.covers(5000, 10) and reg.covers(5009, 1)
+    assert not reg.covers(999, 2)       # starts before a range
+    assert not reg.covers(1050, 51)     # runs past its end
+    assert not reg.covers(1100, 1)      # the gap after a range
+    assert not reg.covers(2400, 200)    # crosses the end of the third
+    assert not reg.covers(10, 1) and not reg.covers(6000, 1)
+    assert not PinnedRegistry().covers(0, 0)
