@@ -166,7 +166,7 @@ SERVE_POOL = 1000  # distinct curves drawn like the mixed workload, cycled by ar
 
 
 def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=50,
-                copy_threads=4, pinned_inputs=False):
+                copy_threads=4):
     """Open-loop serving: Poisson arrivals (rate curves/s) of curves drawn like
     the mixed workload, device-memory budget `budget_gb`; latency from the
     scheduled arrival to the result in host memory."""
@@ -177,15 +177,6 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
     capacity = int(budget_gb * 1e9) // BYTES_PER_SAMPLE
     results = []
     ex = GpuExecutor(capacity, max_curves=4096, max_W=721, copy_threads=copy_threads)
-    if pinned_inputs:  # the client keeps its curves in pinned memory: no staging copy
-        pinned = []
-        for f, t, W in pool:
-            pf = ex.pinned_empty(f.size, np.float32)
-            pt = ex.pinned_empty(t.size, np.float64)
-            pf[:] = f
-            pt[:] = t
-            pinned.append((pf, pt, W))
-        pool = pinned
     srv = Server(ex)
     for i in range(8):  # warm up: capture both graph slots, touch the pinned pool
         srv.submit(*pool[i]).result()
@@ -195,8 +186,7 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
         keep = (lambda i: i % oracle_every == 0) if check_oracle else None
         summary, kept = run_open_loop(srv, pool, arrivals, keep)
         entry = {"rate_curves_per_s": rate, "seconds": seconds, "requests": int(arrivals.size),
-                 "budget_gb": budget_gb, "inputs": "pinned" if pinned_inputs else "pageable",
-                 **summary}
+                 "budget_gb": budget_gb, **summary}
         if check_oracle and kept:
             import oracle
             oracle.build(force=False)
@@ -251,9 +241,6 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-threads", type=int, default=4,
                     help="host threads for pinned staging and result copies in serving")
-    ap.add_argument("--pinned-inputs", action="store_true",
-                    help="serving: the client holds its curves in pinned memory, so each "
-                         "group is uploaded straight from it (no staging copy)")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--no-serve-leg", action="store_true",
                     help="skip the short serving measurement of the default run")
@@ -288,8 +275,7 @@ def main(argv=None):
     if args.serve:
         rates = [float(r) for r in args.rates.split(",")]
         out = serve_sweep(rates, args.serve_seconds, args.budget_gb, log,
-                          check_oracle=not args.no_cpu_baseline, copy_threads=args.copy_threads,
-                          pinned_inputs=args.pinned_inputs)
+                          check_oracle=not args.no_cpu_baseline, copy_threads=args.copy_threads)
         print(json.dumps(out), flush=True)
         return 0
 

@@ -31,7 +31,6 @@ with ``FakeExecutor``.
 """
 from __future__ import annotations
 
-import bisect
 import itertools
 import threading
 import time as _time
@@ -205,39 +204,26 @@ def _addr(a: np.ndarray) -> int:
     return a.__array_interface__["data"][0]
 
 
-def staging_copies(parts, base: int):
-    """The copy list that stages a group's curves ((flux, time) pairs of
-    contiguous float32 / float64 arrays) at host address `base`: every time
-    array back to back first (8-byte aligned), then every flux array.
-    Returns (dst, src, nbytes, samples) for one batched native copy."""
-    k = len(parts)
-    sizes = np.fromiter((f.size for f, _ in parts), np.int64, k)
-    n = int(sizes.sum())
-    pos = np.zeros(k, np.int64)
-    np.cumsum(sizes[:-1], out=pos[1:])
-    dst = np.concatenate([base + 8 * pos, base + 8 * n + 4 * pos]).astype(np.uint64)
-    src = np.fromiter(itertools.chain((_addr(t) for _, t in parts),
-                                      (_addr(f) for f, _ in parts)), np.uint64, 2 * k)
-    nbytes = np.concatenate([8 * sizes, 4 * sizes])
-    return dst, src, nbytes, n
-
-
-class PinnedRegistry:
-    """Host address ranges known to be pinned (page-locked) memory, so that
-    an array inside one can be the source of an asynchronous upload."""
-
-    def __init__(self):
-        self._starts: list = []
-        self._ends: list = []
-
-    def add(self, start: int, nbytes: int):
-        i = bisect.bisect_left(self._starts, start)
-        self._starts.insert(i, int(start))
-        self._ends.insert(i, int(start) + int(nbytes))
-
-    def covers(self, start: int, nbytes: int) -> bool:
-        i = bisect.bisect_right(self._starts, start) - 1
-        return i >= 0 and start + nbytes <= self._ends[i]
+def staging_copies_many(groups_parts, bases):
+    """The copy list that stages several groups at once: group g's curves
+    ((flux, time) pairs of contiguous float32 / float64 arrays) at host
+    address bases[g], every time array back to back first (8-byte aligned
+    when the base is), then every flux array.  Returns (dst, src, nbytes)
+    for one batched native copy."""
+    k = [len(p) for p in groups_parts]
+    flat = [fp for p in groups_parts for fp in p]
+    m = len(flat)
+    sizes = np.fromiter((f.size for f, _ in flat), np.int64, m)
+    gid = np.repeat(np.arange(len(k)), k)
+    first = np.concatenate([[0], np.cumsum(k)[:-1]]).astype(np.int64)
+    csum = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = csum[:-1] - csum[first][gid]              # sample position inside its group
+    n_g = csum[first + np.asarray(k)] - csum[first]  # samples per group
+    base = np.asarray(bases, np.int64)[gid]
+    dst = np.concatenate([base + 8 * pos, base + 8 * n_g[gid] + 4 * pos]).astype(np.uint64)
+    src = np.fromiter(itertools.chain((_addr(t) for _, t in flat), (_addr(f) for f, _ in flat)),
+                      np.uint64, 2 * m)
+    return dst, src, np.concatenate([8 * sizes, 4 * sizes])
 
 
 class PinnedRing:
@@ -326,9 +312,6 @@ class GpuExecutor:
         self._trend_ptr = self.trend.data_ptr()
         self._copy_stream_ptr = int(self.copy_stream.cuda_stream)
         self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
-        self._registry = PinnedRegistry()  # client arrays from pinned_empty()
-        self._client_pinned: list = []
-        self.direct_uploads = 0    # groups uploaded straight from client memory
         # seconds spent in each part of staging and launching (diagnostics)
         self.phase_s = {"stage_alloc": 0.0, "stage_list": 0.0, "stage_copy": 0.0,
                         "h2d": 0.0, "launch_plan": 0.0, "d2h": 0.0, "results": 0.0}
@@ -342,97 +325,53 @@ class GpuExecutor:
         tok, start = got
         return tok, ring.buf[start:start + int(nbytes)], ring.mem[start:start + int(nbytes)]
 
-    def pinned_empty(self, n: int, dtype) -> np.ndarray:
-        """A host array in pinned memory, kept for the executor's lifetime.
-        A group whose requests all hold their flux and time in such arrays is
-        uploaded straight from them, without the staging copy; the caller
-        leaves those arrays unchanged until the request's result arrives."""
-        dt = np.dtype(dtype)
-        t = self.torch.empty(max(1, int(n)) * dt.itemsize, dtype=self.torch.uint8,
-                             pin_memory=True)
-        self._client_pinned.append(t)
-        arr = t.numpy().view(dt)[:int(n)]
-        self._registry.add(_addr(arr), arr.nbytes)
-        return arr
-
-    def _direct_copies(self, offset: int, parts):
-        """(dst, src, nbytes) of the host-to-device copies that upload a group
-        straight from its requests' pinned arrays."""
-        k = len(parts)
-        sizes = np.fromiter((f.size for f, _ in parts), np.int64, k)
-        pos = np.zeros(k, np.int64)
-        np.cumsum(sizes[:-1], out=pos[1:])
-        dst = np.concatenate([self._time_ptr + 8 * (offset + pos),
-                              self._flux_ptr + 4 * (offset + pos)]).astype(np.uint64)
-        src = np.fromiter(itertools.chain((_addr(t) for _, t in parts),
-                                          (_addr(f) for f, _ in parts)), np.uint64, 2 * k)
-        return dst, src, np.concatenate([8 * sizes, 4 * sizes])
-
-    def _is_direct(self, parts) -> bool:
-        reg = self._registry
-        return all(reg.covers(_addr(f), f.nbytes) and reg.covers(_addr(t), t.nbytes)
-                   for f, t in parts)
-
     def upload_many(self, groups):
-        """Upload several groups ((offset, parts) pairs): those held wholly in
-        pinned client memory with one native call and one event between them,
-        the rest through staging.  Returns one upload handle per group."""
-        out = [None] * len(groups)
-        direct = []
-        for i, (offset, parts) in enumerate(groups):
+        """Upload several groups ((offset, parts) pairs, parts = the requests'
+        (flux, time) arrays): one pinned ring block holds them all (each
+        group's times, then its fluxes), one batched native copy fills it, one
+        native call enqueues every host-to-device copy, and one event marks
+        them done.  Returns one upload handle per group; the first carries the
+        ring block, which is released when its step completes (every group's
+        copy is done by then: the steps wait on the shared event)."""
+        clk = _time.perf_counter
+        ph = self.phase_s
+        if not groups:
+            return []
+        t0 = clk()
+        sizes = []
+        for offset, parts in groups:
             n = sum(f.size for f, _ in parts)
             if not (0 <= offset and offset + n <= self.capacity):
                 raise ValueError("upload range [%d, %d) outside the arena" % (offset, offset + n))
-            if self._is_direct(parts):
-                direct.append(i)
-            else:
-                out[i] = self.stage_upload(offset, parts)
-        if direct:
-            t0 = _time.perf_counter()
-            cps = [self._direct_copies(*groups[i]) for i in direct]
-            self._copy_async(np.concatenate([c[0] for c in cps]),
-                             np.concatenate([c[1] for c in cps]),
-                             np.concatenate([c[2] for c in cps]), self._H2D,
-                             self._copy_stream_ptr)
-            ev = self.torch.cuda.Event()
-            ev.record(self.copy_stream)
-            for i in direct:
-                out[i] = (ev, None, None)
-            self.direct_uploads += len(direct)
-            self.phase_s["h2d"] += _time.perf_counter() - t0
-        return out
-
-    def stage_upload(self, offset: int, parts):
-        """Copy the group's curves ((flux, time) pairs) into pinned staging in
-        one native call and start one host-to-device copy per array on the
-        copy stream -- or, when every array is in memory from pinned_empty(),
-        upload straight from it."""
-        torch = self.torch
-        n = sum(f.size for f, _ in parts)
-        if not (0 <= offset and offset + n <= self.capacity):
-            raise ValueError("upload range [%d, %d) outside the arena" % (offset, offset + n))
-        if self._is_direct(parts):
-            return self.upload_many([(offset, parts)])[0]
-        clk = _time.perf_counter
-        ph = self.phase_s
-        t0 = clk()
-        tok, tbuf, mem = self._pinned(self.ring_in, 12 * n)
-        base = _addr(mem)
+            sizes.append(n)
+        align = PinnedRing.ALIGN
+        spans = [(12 * n + align - 1) // align * align for n in sizes]
+        tok, tbuf, mem = self._pinned(self.ring_in, sum(spans))
         t1 = clk()
-        dst, src, nbytes, _ = staging_copies(parts, base)
+        bases = _addr(mem) + np.concatenate([[0], np.cumsum(spans[:-1])]).astype(np.int64)
+        dst, src, nbytes = staging_copies_many([parts for _, parts in groups], bases)
+        offs = np.fromiter((o for o, _ in groups), np.int64, len(groups))
+        ns = np.asarray(sizes, np.int64)
+        h_dst = np.concatenate([self._time_ptr + 8 * offs, self._flux_ptr + 4 * offs])
+        h_src = np.concatenate([bases, bases + 8 * ns])
+        h_nb = np.concatenate([8 * ns, 4 * ns])
         t2 = clk()
         self._copy(dst, src, nbytes, self.copy_threads)
         t3 = clk()
-        self._copy_async([self._time_ptr + 8 * offset, self._flux_ptr + 4 * offset],
-                         [base, base + 8 * n], [8 * n, 4 * n], self._H2D, self._copy_stream_ptr)
-        ev = torch.cuda.Event()
+        self._copy_async(h_dst.astype(np.uint64), h_src.astype(np.uint64), h_nb, self._H2D,
+                         self._copy_stream_ptr)
+        ev = self.torch.cuda.Event()
         ev.record(self.copy_stream)
         t4 = clk()
         ph["stage_alloc"] += t1 - t0
         ph["stage_list"] += t2 - t1
         ph["stage_copy"] += t3 - t2
         ph["h2d"] += t4 - t3
-        return (ev, tok, tbuf)
+        return [(ev, tok, tbuf)] + [(ev, None, None)] * (len(groups) - 1)
+
+    def stage_upload(self, offset: int, parts):
+        """Upload one group (see upload_many)."""
+        return self.upload_many([(offset, parts)])[0]
 
     def upload(self, offset: int, flux: np.ndarray, time: np.ndarray):
         return self.stage_upload(offset, [(flux, time)])
@@ -602,6 +541,9 @@ class Server:
                 self.stats.rejected += 1
             fut.set_exception(e)
             return fut
+        if flux.size == 0:  # nothing to compute: resolved at once
+            fut.set_result(np.zeros(0, np.float32))
+            return fut
         req = Request(next(self._ids), flux, time_, int(W), float(alpha), float(c), int(iters),
                       arrival, fut)
         submitted = self.clock()
@@ -629,7 +571,6 @@ class Server:
         with self._lock:
             out = self.stats.summary(self.arena)
             out["pinned_fallbacks"] = getattr(self.ex, "pinned_fallbacks", None)
-            out["direct_uploads"] = getattr(self.ex, "direct_uploads", None)
             ph = getattr(self.ex, "phase_s", None)
             if ph is not None:
                 out["executor_phase_s"] = dict(ph)
@@ -643,8 +584,7 @@ class Server:
             if ph is not None:
                 for k in ph:
                     ph[k] = 0.0
-            if hasattr(self.ex, "direct_uploads"):
-                self.ex.direct_uploads = 0
+
             self.arena.high_water = self.arena.used
 
     # -- scheduler ---------------------------------------------------------

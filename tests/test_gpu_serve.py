@@ -86,36 +86,3 @@ def test_copy_async_round_trip(torch):
     s.synchronize()
     assert torch.equal(back, host)
     assert not dev[total:].any().item()
-
-
-def test_pinned_client_arrays_upload_directly(torch):
-    """Requests whose arrays come from the executor's pinned memory skip the
-    staging copy and give results bit-identical to the same curves sent from
-    ordinary host memory."""
-    import paper_2604_06602_amd as umi
-    from paper_2604_06602_amd.serve import GpuExecutor, Server
-    curves = []
-    for i in range(12):
-        f, t, W = synth.curve_for(4, i)
-        L = min(f.size, 20000)
-        curves.append((f[:L], t[:L], W))
-    ex = GpuExecutor(2_000_000, max_curves=64, max_W=721, staging_bytes=64 << 20)
-    srv = Server(ex)
-    plain = [fu.result(timeout=60) for fu in [srv.submit(f, t, W) for f, t, W in curves]]
-    assert ex.direct_uploads == 0
-    pinned = []
-    for f, t, W in curves:
-        pf = ex.pinned_empty(f.size, np.float32)
-        pt = ex.pinned_empty(t.size, np.float64)
-        pf[:] = f
-        pt[:] = t
-        pinned.append((pf, pt, W))
-    direct = [fu.result(timeout=60) for fu in [srv.submit(f, t, W) for f, t, W in pinned]]
-    assert ex.direct_uploads > 0
-    srv.close()
-    for a, b in zip(plain, direct):
-        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
-    f, t, W = curves[0]
-    alone, _ = umi.detrend(torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda(), W)
-    torch.cuda.synchronize()
-    assert np.array_equal(alone.cpu().numpy().view(np.uint32), direct[0].view(np.uint32))

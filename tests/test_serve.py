@@ -252,30 +252,6 @@ def test_pinned_ring_blocks_never_overlap(ops):
     assert ring.alloc(8192) is not None  # everything came back
 
 
-def test_staging_copies_lay_out_times_then_fluxes():
-    """The executor's staging copy list, run by the native batched copy into
-    an ordinary host buffer: every time array back to back, then every flux
-    array, each sample written once and nothing outside the staged bytes."""
-    from paper_2604_06602_amd import host_copy_many
-    from paper_2604_06602_amd.serve import staging_copies
-    rng = np.random.default_rng(0)
-    for trial in range(20):
-        parts = []
-        for _ in range(int(rng.integers(1, 40))):
-            L = int(rng.integers(0, 3000)) if trial % 5 else int(rng.integers(1, 400000))
-            parts.append((rng.random(L).astype(np.float32), rng.random(L) * 27.0))
-        n = sum(f.size for f, _ in parts)
-        buf = np.zeros(12 * n + 64, np.uint8)
-        dst, src, nbytes, got_n = staging_copies(parts, buf.ctypes.data)
-        assert got_n == n
-        host_copy_many(dst, src, nbytes, threads=1 + trial % 6)
-        t = buf[:8 * n].view(np.float64)
-        f = buf[8 * n:12 * n].view(np.float32)
-        assert np.array_equal(t, np.concatenate([p[1] for p in parts]))
-        assert np.array_equal(f, np.concatenate([p[0] for p in parts]))
-        assert not buf[12 * n:].any()
-
-
 def test_steps_respect_the_sample_limit_and_big_requests_still_run():
     """Groups and steps stay within max_step_samples, except a lone request
     larger than the limit, which forms a step of its own."""
@@ -317,19 +293,42 @@ def test_upload_failure_fails_every_request_and_close_reports_it():
         srv.close(timeout=10)
 
 
-def test_pinned_registry_covers_only_whole_ranges():
-    """The executor uploads straight from a client array only if the array
-    lies wholly inside one registered pinned range."""
-    from paper_2604_06602_amd.serve import PinnedRegistry
-    reg = PinnedRegistry()
-    reg.add(1000, 100)
-    reg.add(5000, 10)
-    reg.add(2000, 500)
-    assert reg.covers(1000, 100) and reg.covers(1050, 50) and reg.covers(2100, 400)
-    assert reg.covers(5000, 10) and reg.covers(5009, 1)
-    assert not reg.covers(999, 2)       # starts before a range
-    assert not reg.covers(1050, 51)     # runs past its end
-    assert not reg.covers(1100, 1)      # the gap after a range
-    assert not reg.covers(2400, 200)    # crosses the end of the third
-    assert not reg.covers(10, 1) and not reg.covers(6000, 1)
-    assert not PinnedRegistry().covers(0, 0)
+def test_staging_copies_many_lays_out_each_group_at_its_base():
+    """Several groups staged at once: group g's times then fluxes at its own
+    base address, each sample written once, nothing between the groups."""
+    from paper_2604_06602_amd import host_copy_many
+    from paper_2604_06602_amd.serve import staging_copies_many
+    rng = np.random.default_rng(3)
+    for trial in range(10):
+        groups = []
+        for _ in range(int(rng.integers(1, 6))):
+            parts = []
+            for _ in range(int(rng.integers(1, 8))):
+                L = int(rng.integers(0, 5000))
+                parts.append((rng.random(L).astype(np.float32), rng.random(L) * 27.0))
+            groups.append(parts)
+        spans = [(12 * sum(f.size for f, _ in g) + 255) // 256 * 256 for g in groups]
+        buf = np.zeros(sum(spans) + 256, np.uint8)
+        base0 = (buf.ctypes.data + 255) // 256 * 256
+        off0 = base0 - buf.ctypes.data
+        bases = base0 + np.concatenate([[0], np.cumsum(spans[:-1])]).astype(np.int64)
+        dst, src, nbytes = staging_copies_many(groups, bases)
+        host_copy_many(dst, src, nbytes, threads=1 + trial % 4)
+        at = off0
+        for g, span in zip(groups, spans):
+            n = sum(f.size for f, _ in g)
+            t = buf[at:at + 8 * n].view(np.float64)
+            f = buf[at + 8 * n:at + 12 * n].view(np.float32)
+            assert np.array_equal(t, np.concatenate([p[1] for p in g]))
+            assert np.array_equal(f, np.concatenate([p[0] for p in g]))
+            assert not buf[at + 12 * n:at + span].any()
+            at += span
+
+
+def test_empty_request_resolves_without_a_step():
+    srv = Server(FakeExecutor(1000, delay=0.001))
+    fu = srv.submit(np.zeros(0, np.float32), W=5)
+    res = fu.result(timeout=10)
+    assert res.dtype == np.float32 and res.size == 0
+    assert srv.summary()["steps"] == 0
+    srv.close()
