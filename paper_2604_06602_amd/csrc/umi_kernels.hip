@@ -13,19 +13,25 @@
 //                       valid samples compacted in LDS, sorts (key, index) pairs
 //                       of the staged samples once (bitonic network in LDS), and
 //                       builds a wavelet matrix over the sorted ranks.  Every
-//                       lane then takes one window at a time:
+//                       lane then takes up to three consecutive windows:
 //                         Phase 1 (Section 2.1): exact median as the k-th
 //                           smallest rank in the window's index range, one
 //                           O(log N) wavelet descent -- the sort is shared by
-//                           all windows of the tile;
+//                           all windows of the tile.  Tiles of full windows
+//                           with W <= 31 skip the sort and take their medians
+//                           from register networks instead;
 //                         Phase 2 (Section 2.2, Eq. 1): upper-RMS scale;
 //                         Phase 3 (Section 2.3, Eqs. 2-4): asymmetric bisquare
 //                           iterations in the residual form
-//                           mu <- mu + sum(w u) / (k sum(w)), k = 1/(c s),
-//                           which is Eq. 4 rewritten around the current mu.
-//                       Launched either persistently (a grid sized to the chip
-//                       pops tiles from a device counter) or one workgroup per
-//                       tile.
+//                           mu <- mu + sum(w v) / (k sum(w)), v = k (x - mu),
+//                           k = A/(c s), A = (1 + alpha)/2: Eq. 4 rewritten
+//                           around the current mu, with Eq. 2's two branches
+//                           folded into one expression of v.
+//                       Windows that share samples and have the same length
+//                       are summed in one fused sweep (one LDS read per sample
+//                       for all of them).  Launched either persistently (a
+//                       grid sized to the chip pops tiles from a device
+//                       counter) or one workgroup per tile.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
