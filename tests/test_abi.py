@@ -304,3 +304,17 @@ def test_copy_async_rejects_bad_arguments(lib):
             lib.copy_async(args["dst"], args["src"], args["nbytes"], args["kind"], 0)
     f = lib.lib.umi_copy_async
     assert f(None, None, None, 1, 1, None) == 1 and f(None, None, None, -1, 1, None) == 1
+
+
+def test_host_copy_many_with_many_small_copies(lib):
+    """Tens of thousands of tiny copies (pieces index the copy list by binary
+    search): every destination gets its own source's bytes."""
+    rng = np.random.default_rng(11)
+    n = 20000
+    sizes = rng.integers(0, 40, n)
+    src = rng.integers(0, 256, int(sizes.sum()), dtype=np.uint8)
+    dst = np.zeros_like(src)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    perm = rng.permutation(n)  # scatter the copies in a shuffled order
+    lib.host_copy_many(dst.ctypes.data + offs[perm], src.ctypes.data + offs[perm], sizes[perm], 8)
+    assert np.array_equal(dst, src)
