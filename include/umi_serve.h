@@ -31,7 +31,8 @@ extern "C" {
  * thread and threads - 1 pool threads, started on first use and kept for the
  * life of the process) take in turn.  The regions of different copies must not
  * overlap (the result is then undefined, as for memcpy).  Calls from several
- * threads are safe; they run one after another.
+ * threads are safe: those that use the pool take it one after another, and a
+ * call with one piece, or with threads = 1, copies on the calling thread.
  * Errors: n < 0, threads < 1 or > UMI_HOST_COPY_MAX_THREADS, a NULL array with
  * n > 0, a negative size, or a NULL pointer with a positive size give
  * UMI_ERR_INVALID_ARG before anything is copied.  n = 0 is a no-op. */
