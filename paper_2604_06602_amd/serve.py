@@ -584,7 +584,6 @@ class Server:
             if ph is not None:
                 for k in ph:
                     ph[k] = 0.0
-
             self.arena.high_water = self.arena.used
 
     # -- scheduler ---------------------------------------------------------
