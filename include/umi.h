@@ -72,7 +72,11 @@ typedef enum {
 } umi_mode;
 
 /* Tuning knobs; zero in a field means "use the library's choice" (its
- * built-in defaults, or the tuning table loaded with umi_set_tuning). */
+ * built-in defaults, or the tuning table loaded with umi_set_tuning).  With
+ * tile = 0, a batch that the chosen tiles would cut into fewer tiles than the
+ * device has compute units runs with tiles of at most 1024, then 512 output
+ * positions, so that more of the chip shares it; results never depend on
+ * the tiling. */
 typedef struct {
     int32_t mode;          /* umi_mode */
     int32_t tile;          /* output positions per tile (0 = auto) */
