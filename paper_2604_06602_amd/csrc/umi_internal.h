@@ -14,6 +14,8 @@ constexpr int kWords = kStageMax / 64 + 1;  // bit-vector words incl. sentinel
 constexpr int kMainThreads = 512;            // threads per main-kernel workgroup
 constexpr int kMaxTile = 3 * kMainThreads;   // output positions per tile: <= 3 per lane
 constexpr int kPrepThreads = 256;            // threads per pre-pass workgroup
+constexpr int kPrepWideThreads = 1024;       // ... when a launch covers few curves
+constexpr int kPrepWideCurves = 64;          // "few": at most this many
 constexpr int kPrepItems = 4;                // samples per pre-pass thread per chunk
 constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1
 constexpr double kGapDays = 0.5;             // segment break threshold (days)

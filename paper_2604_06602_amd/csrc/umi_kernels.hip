@@ -76,7 +76,8 @@ __device__ __forceinline__ void wave_incl_latest(int& idx, double& t)
     }
 }
 
-// Exclusive block-wide sum over kPrepThreads threads; `total` gets the sum.
+// Exclusive block-wide sum over NT threads; `total` gets the sum.
+template <int NT>
 __device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
 {
     const int incl = wave_incl_sum(x);
@@ -85,7 +86,7 @@ __device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
     __syncthreads();
     int before = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kPrepThreads / 64; ++i) {
+    for (int i = 0; i < NT / 64; ++i) {
         int v = sh[i];
         before += (i < w) ? v : 0;
         tot += v;
@@ -98,16 +99,17 @@ __device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
 // ---------------------------------------------------------------------------
 // Pre-pass: segments and tiles.
 
-__global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) void umi_prepass_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
     const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_first,
     int32_t* __restrict__ segid, int4* __restrict__ segtab,
     int2* __restrict__ tiles, uint32_t* __restrict__ counter)
 {
-    __shared__ int sh_li[kPrepThreads / 64];
-    __shared__ double sh_lt[kPrepThreads / 64];
-    __shared__ int sh_a[kPrepThreads / 64];
-    __shared__ int sh_b[kPrepThreads / 64];
+    __shared__ int sh_li[NT / 64];
+    __shared__ double sh_lt[NT / 64];
+    __shared__ int sh_a[NT / 64];
+    __shared__ int sh_b[NT / 64];
 
     if (counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
     const int cidx = curve_first + (int)blockIdx.x;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
     const CurveDesc cd = curves[cidx];
 
     const int ntiles = cd.len > 0 ? (cd.len + cd.tile - 1) / cd.tile : 0;
-    for (int t = threadIdx.x; t < ntiles; t += kPrepThreads)
+    for (int t = threadIdx.x; t < ntiles; t += NT)
         tiles[cd.tile_base + t] = make_int2(cidx, t * cd.tile);
 
     const float* f = flux + cd.off;
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
 
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
-    constexpr int kChunk = kPrepThreads * kPrepItems;
+    constexpr int kChunk = NT * kPrepItems;
 
     // The next chunk's flux and times are loaded while the current one is
     // scanned, so the loads' latency overlaps the block scans.
@@ -184,10 +186,10 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
             sh_lt[w] = lt;
         }
         int tot_cnt;
-        const int ex_cnt = block_excl_sum(a_cnt, sh_a, tot_cnt);  // syncs
+        const int ex_cnt = block_excl_sum<NT>(a_cnt, sh_a, tot_cnt);  // syncs
         int blk_i = -1;
         double blk_t = 0.0;
-        for (int i = 0; i < kPrepThreads / 64; ++i) {
+        for (int i = 0; i < NT / 64; ++i) {
             const int wi = sh_li[i];
             if (wi > blk_i) {
                 blk_i = wi;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(kPrepThreads) void umi_prepass_kernel(
             }
         }
         int tot_st;
-        const int ex_st = block_excl_sum(n_st, sh_b, tot_st);  // syncs
+        const int ex_st = block_excl_sum<NT>(n_st, sh_b, tot_st);  // syncs
         {
             int s = c_ns + ex_st - 1;
             int pi = ex_i;               // previous valid index
@@ -935,8 +937,17 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
                           int4* segtab, int2* tiles, uint32_t* counter, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(umi_prepass_kernel, dim3(grid), dim3(kPrepThreads), 0, stream, flux, time,
-                       hdr, curves, curve_first, segid, segtab, tiles, counter);
+    // A launch over few curves walks each curve with a 1024-thread workgroup
+    // (a quarter as many chunks in sequence); many curves fill the chip with
+    // 256-thread workgroups, one per curve.
+    if (grid <= kPrepWideCurves)
+        hipLaunchKernelGGL(umi_prepass_kernel<kPrepWideThreads>, dim3(grid),
+                           dim3(kPrepWideThreads), 0, stream, flux, time, hdr, curves,
+                           curve_first, segid, segtab, tiles, counter);
+    else
+        hipLaunchKernelGGL(umi_prepass_kernel<kPrepThreads>, dim3(grid), dim3(kPrepThreads), 0,
+                           stream, flux, time, hdr, curves, curve_first, segid, segtab, tiles,
+                           counter);
     return hipGetLastError();
 }
 
