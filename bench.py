@@ -184,7 +184,9 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
         arrivals = synth.poisson_arrivals(rate, seconds, seed=int(rate))
         srv.reset_stats()
         keep = (lambda i: i % oracle_every == 0) if check_oracle else None
-        summary, kept = run_open_loop(srv, pool, arrivals, keep)
+        summary, kept = run_open_loop(
+            srv, pool, arrivals, keep,
+            progress=lambda n, sec: log("rate %g/s: %d submitted after %.0f s" % (rate, n, sec)))
         entry = {"rate_curves_per_s": rate, "seconds": seconds, "requests": int(arrivals.size),
                  "budget_gb": budget_gb, **summary}
         if check_oracle and kept:

@@ -778,10 +778,13 @@ class Server:
 # open-loop driver
 
 
-def run_open_loop(server: Server, curves, arrivals, keep_results=None, pause_gc=True):
+def run_open_loop(server: Server, curves, arrivals, keep_results=None, pause_gc=True,
+                  progress=None, progress_every: float = 10.0):
     """Submit ``curves[i % len(curves)]`` at times ``arrivals`` (seconds from
     the start) regardless of completions, then wait for all of them.
-    ``keep_results(i)`` selects the requests whose results are returned.
+    ``keep_results(i)`` selects the requests whose results are returned;
+    ``progress(submitted, seconds)``, if given, is called about every
+    ``progress_every`` seconds while requests are being submitted.
     With ``pause_gc`` the cyclic garbage collector is frozen and paused for
     the measured window (its full sweeps over ~1e5 live requests otherwise
     stall both the scheduler and the arrival generator for tens of ms).
@@ -792,14 +795,14 @@ def run_open_loop(server: Server, curves, arrivals, keep_results=None, pause_gc=
         gc.freeze()
         gc.disable()
     try:
-        return _open_loop(server, curves, arrivals, keep_results)
+        return _open_loop(server, curves, arrivals, keep_results, progress, progress_every)
     finally:
         if pause_gc:
             gc.enable()
             gc.unfreeze()
 
 
-def _open_loop(server, curves, arrivals, keep_results):
+def _open_loop(server, curves, arrivals, keep_results, progress=None, progress_every=10.0):
     # Results are taken as they complete and dropped unless kept, as a client
     # would: holding every result of a minute at 20,000 curves/s would pin
     # about 100 GB of host memory and stall both threads in page faults.
@@ -814,9 +817,13 @@ def _open_loop(server, curves, arrivals, keep_results):
             if keep_results is not None and keep_results(i):
                 kept[i] = (i % len(curves), res)
 
+    next_report = t0 + progress_every
     for i, at in enumerate(arrivals):
         target = t0 + float(at)
         drain(False)
+        if progress is not None and target >= next_report:
+            progress(i, target - t0)
+            next_report += progress_every
         while True:
             now = server.clock()
             if now >= target:

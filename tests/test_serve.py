@@ -332,3 +332,16 @@ def test_empty_request_resolves_without_a_step():
     assert res.dtype == np.float32 and res.size == 0
     assert srv.summary()["steps"] == 0
     srv.close()
+
+
+def test_open_loop_reports_progress():
+    from paper_2604_06602_amd.serve import run_open_loop
+    srv = Server(FakeExecutor(100000, delay=0.0005))
+    curves = [(np.ones(200, np.float32), np.arange(200) * 0.01, 5)]
+    arrivals = np.linspace(0.0, 0.35, 60)
+    seen = []
+    summary, _ = run_open_loop(srv, curves, arrivals, progress=lambda n, s: seen.append((n, s)),
+                               progress_every=0.1)
+    srv.close()
+    assert summary["completed"] == 60
+    assert len(seen) >= 3 and all(b[0] > a[0] for a, b in zip(seen, seen[1:]))
