@@ -193,15 +193,21 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
             import oracle
             oracle.build(force=False)
             rng = np.random.default_rng(0)
-            worst = 0.0
+            worst, compared, nan_mismatch = 0.0, 0, 0
             for i, (ci, res) in kept.items():
                 f, t, W = pool[ci]
                 idx = np.unique(rng.integers(0, f.size, 64))
                 o_tr, _ = oracle.detrend_at(f, t, W, idx)
                 ok = ~np.isnan(o_tr)
+                g = res[idx]
+                nan_mismatch += int(np.count_nonzero(np.isnan(g) != ~ok))
                 if ok.any():
-                    worst = max(worst, float(np.max(np.abs(res[idx][ok] - o_tr[ok]) / np.abs(o_tr[ok]))))
+                    rel = np.abs(g[ok] - o_tr[ok]) / np.abs(o_tr[ok])
+                    worst = max(worst, float(np.max(np.where(np.isnan(rel), np.inf, rel))))
+                    compared += int(ok.sum())
             entry["oracle_checked_requests"] = len(kept)
+            entry["oracle_compared_samples"] = compared
+            entry["nan_pattern_mismatches"] = nan_mismatch
             entry["max_rel_err_vs_fp64_oracle"] = worst
         log("rate %g/s: p50 %.2f ms, p99 %.2f ms, %.0f curves/s, %d steps"
             % (rate, entry["p50_ms"] or -1, entry["p99_ms"] or -1, entry["curves_per_s"] or -1,

@@ -815,7 +815,8 @@ def _open_loop(server, curves, arrivals, keep_results, progress=None, progress_e
             i, fu = pending.popleft()
             res = fu.result()
             if keep_results is not None and keep_results(i):
-                kept[i] = (i % len(curves), res)
+                # a copy: the result is a view of its whole group's array
+                kept[i] = (i % len(curves), np.array(res))
 
     next_report = t0 + progress_every
     for i, at in enumerate(arrivals):
