@@ -11,4 +11,5 @@ from .lightcurves import (  # noqa: F401
     curve_for,
     draw_config3_curve,
     poisson_arrivals,
+    white_noise_windows,
 )

@@ -225,3 +225,16 @@ def poisson_arrivals(rate_hz: float, duration_s: float, seed: int = 0) -> np.nda
     while t[-1] < duration_s:
         t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate_hz, n_max))])
     return t[t < duration_s]
+
+
+def white_noise_windows(n_windows: int, W: int = 361, sigma: float = 1e-3, seed: int = 0):
+    """Flat white-noise star for the bias check of Sections 2.4 and 4.1: one
+    float32 curve 1 + N(0, sigma^2) of n_windows * W samples (2-min cadence),
+    and the centres of its n_windows disjoint full windows of W samples,
+    which are therefore independent draws.  Returns (flux, time, centres)."""
+    rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 7, seed]))
+    n = n_windows * W
+    f = (1.0 + rng.normal(0.0, sigma, n)).astype(np.float32)
+    t = np.arange(n, dtype=np.float64) * (2 * MIN)
+    centres = (W - 1) // 2 + W * np.arange(n_windows, dtype=np.int64)
+    return f, t, centres

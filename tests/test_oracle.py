@@ -17,6 +17,7 @@ from hypothesis import given, settings
 from hypothesis import strategies as st
 
 from tests import bruteforce as bf
+from tests import whitenoise as wn
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
 SCALE = 0.6745
@@ -466,6 +467,47 @@ def test_paper_bias_direction_white_noise(oracle_lib):
     assert abs(out[1.0]) < 0.05
     assert 0.2 < out[2.0] < 0.7
     assert out[10.0] > 2.5 * out[2.0]
+
+
+def test_white_noise_bias_matches_monte_carlo(oracle_lib):
+    """Sections 2.4 and 4.1, pinned to the Monte-Carlo values within half a
+    unit of their last printed digit plus three combined standard errors (this
+    run's and, at equal size, the reference Monte-Carlo's)."""
+    got = wn.bias_offsets(lambda f, t, W, idx, a, c: oracle_lib.detrend_at(f, t, W, idx, alpha=a,
+                                                                           c=c)[0])
+    wn.assert_offsets_match(got)
+
+
+# --------------------------------------------------------------------------
+# Hand-worked trajectories (Sections 2.1-2.3)
+
+TRAJ = os.path.join(os.path.dirname(__file__), "golden", "hand_trajectories.txt")
+
+
+def hand_trajectories():
+    rows = []
+    with open(TRAJ) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, a, c, xs, m, s, mus, _note = [p.strip() for p in line.split("|", 7)]
+            rows.append((name, float(a), float(c), [float(v) for v in xs.split(",")], float(m),
+                         float(s), [None if v == "-" else float(v) for v in mus.split(",")]))
+    return rows
+
+
+@pytest.mark.parametrize("row", hand_trajectories(), ids=lambda r: r[0])
+def test_hand_worked_trajectories(oracle_lib, row):
+    """Every iterate mu_k of a worked window equals the hand value (the trend
+    after k iterations), and the median and scale equal theirs."""
+    name, a, c, xs, m, s, mus = row
+    assert len(mus) == 5
+    for k, want in enumerate(mus, start=1):
+        t, med, sc = oracle_lib.window(xs, alpha=a, c=c, iters=k)
+        assert float(med) == m and sc == pytest.approx(s, rel=1e-10, abs=1e-12)
+        if want is not None:
+            assert t == pytest.approx(want, rel=1e-10, abs=1e-12), (name, k, t, want)
 
 
 # --------------------------------------------------------------------------

@@ -59,3 +59,33 @@ def test_pins_catch_mutant(tmp_path, name):
                         os.path.join(ROOT, "tests", "test_oracle.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch: %s\n%s" % (name, r.stdout[-2000:])
+
+
+# Mistakes in the estimate of one window that the hand-worked trajectories
+# and the white-noise bias pin must catch on their own (without the rest of
+# the suite): every iterate of a worked window moves under each of them.
+WINDOW_MUTANTS = [
+    "alpha dropped (Eq. 2)", "alpha on the upper side (Eq. 2)", "weight not squared (Eq. 3)",
+    "scale constant inverted (Section 2.2)", "upper set not strict (Eq. 1)",
+    "upper RMS over n, not n+ (Eq. 1)", "upper median instead of lower",
+    "negative values ordered wrongly", "c dropped from u (Section 2.3)",
+    "unweighted sum in Eq. 4", "one iteration too many",
+]
+
+
+@pytest.mark.parametrize("name", WINDOW_MUTANTS)
+def test_trajectory_pins_alone_catch_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    mut = tmp_path / "umi_oracle_mutant.c"
+    mut.write_text(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle.oracle import compile_oracle
+    lib = compile_oracle(str(mut), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, UMI_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                        "-k", "hand_worked_trajectories or white_noise_bias_matches",
+                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and " failed" in r.stdout, \
+        "trajectory pins did not catch: %s\n%s" % (name, r.stdout[-2000:])
