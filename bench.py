@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 METRIC = "window-estimates/s (1000x18k TESS batch, W=361); p50/p99 latency in serve loop"
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
+TARGET_FRAC = 0.5          # the batched kernel's goal: half the FP32 VALU peak
 
 
 # Algorithmic FP32 work per window sample (add/sub/mul = 1, fma = 2; compares,
@@ -61,42 +62,73 @@ def window_sizes(batch, gap_days: float = 0.5) -> np.ndarray:
     return out
 
 
-def cpu_model() -> str:
-    """The host CPU's model name (Linux), or 'unknown'."""
+def cpu_model() -> dict:
+    """What the host says about its CPU (Linux): the model string, family /
+    model / stepping, clock, and lscpu's view when it is there."""
+    info = {"model_name": "unknown"}
+    keys = {"model name": "model_name", "vendor_id": "vendor", "cpu family": "family",
+            "model": "model", "stepping": "stepping", "cpu MHz": "mhz"}
     try:
         with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+            block = fh.read().split("\n\n")[0]  # the first processor
+        for line in block.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                info[keys[k.strip()]] = v.strip()
     except OSError:
         pass
-    return "unknown"
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                     "CPU max MHz", "Hypervisor vendor"):
+                info["lscpu_" + k.lower().replace(" ", "_").replace("(s)", "s")] = v.strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
 
 
-def cpu_baseline(batch, budget_s: float = 15.0):
+def cpu_baseline(batch, budget_s: float = 15.0, first_curves: int | None = None,
+                 total_windows: int | None = None):
     """The oracle as it stands, on the host's cores, over the first curves of
-    the same workload (about `budget_s` seconds)."""
+    the same workload: about `budget_s` seconds, or exactly `first_curves`
+    curves.  With `total_windows` (the whole workload's finite outputs) the
+    time the oracle would take for all of it is extrapolated at the measured
+    rate."""
     import oracle
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    # one curve per thread, so the probe sees the parallel rate
-    probe = min(int(batch.n_curves), max(8, int(cores)))
-    sub = batch_prefix(batch, probe)
-    t0 = time.perf_counter()
-    oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
-    per_curve = (time.perf_counter() - t0) / probe
-    n = int(min(batch.n_curves, max(probe, round(budget_s / max(per_curve, 1e-6)))))
+    cores = max(1, int(cores))
+    if first_curves is None:
+        # one curve per thread, so the probe sees the parallel rate
+        probe = min(int(batch.n_curves), max(8, cores))
+        sub = batch_prefix(batch, probe)
+        t0 = time.perf_counter()
+        oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
+        per_curve = (time.perf_counter() - t0) / probe
+        n = int(min(batch.n_curves, max(probe, round(budget_s / max(per_curve, 1e-6)))))
+    else:
+        n = int(min(batch.n_curves, first_curves))
     sub = batch_prefix(batch, n)
     t0 = time.perf_counter()
     tr, _ = oracle.detrend_batch(sub.flux, sub.time, sub.lengths, sub.W, n_threads=cores)
     dt = time.perf_counter() - t0
     windows = int(np.isfinite(tr).sum())
-    used = min(int(cores), n)  # the oracle runs one curve per thread
-    return {"value": windows / dt, "unit": "window-estimates/s", "cores": used,
-            "kind": "oracle", "cpu": cpu_model(),
-            "per_core": windows / dt / max(1, used),
-            "sample": "first %d of the %d curves (%d windows), FP64 C oracle, %d threads, %.1f s"
-                      % (n, batch.n_curves, windows, used, dt)}
+    used = min(cores, n)  # the oracle runs one curve per thread
+    out = {"value": windows / dt, "unit": "window-estimates/s", "cores": used,
+           "kind": "oracle", "cpu": cpu_model(),
+           "per_core": windows / dt / max(1, used),
+           "sample": "first %d of the %d curves (%d windows), FP64 C oracle, %d threads, %.1f s"
+                     % (n, batch.n_curves, windows, used, dt)}
+    if total_windows is not None:
+        out["extrapolated_full_workload_s"] = total_windows / (windows / dt)
+        out["extrapolation"] = ("all %d windows of the workload at the sampled rate (curves of "
+                                "this workload are drawn independently, so the first ones are a "
+                                "fair sample of its length and W mix)" % total_windows)
+    return out
 
 
 PROFILE = os.path.join(ROOT, "profiles", "umi_main_kernel__tess_batch_1000x18k_w361.md")
@@ -235,8 +267,9 @@ def main(argv=None):
                          "of 40k-70k, W=25; 3: 10,000 mixed curves of 1k-120k, W in "
                          "{25,121,361,721}, 5%% NaN gaps")
     ap.add_argument("--mode", choices=["persistent", "per-curve"], default="persistent")
-    ap.add_argument("--compare-per-curve", action="store_true",
-                    help="also time one launch per curve on the same batch")
+    ap.add_argument("--no-compare-per-curve", action="store_true",
+                    help="skip timing one launch per curve on the same batch (the comparison "
+                         "runs by default on workloads 1-3)")
     ap.add_argument("--tuning", default="auto",
                     help="'auto' (the committed tuning table for this GPU, if any), 'none' "
                          "(built-in defaults) or a table file")
@@ -360,7 +393,7 @@ def main(argv=None):
     fma_peak = measured_fma_peak(torch, stream, log)
 
     per_curve = None
-    if args.compare_per_curve:
+    if not args.no_compare_per_curve and args.workload != 0:
         other = umi.MODE_PER_CURVE if mode == umi.MODE_PERSISTENT else umi.MODE_PERSISTENT
         k = max(3, args.steps // 4)
         for _ in range(2):
@@ -420,6 +453,8 @@ def main(argv=None):
         "roofline": {"bound": "alu", "kernel": "umi_main_kernel",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(),
+                     "target_frac": TARGET_FRAC,
+                     "target_met": achieved / PEAK_FP32_TFLOPS >= TARGET_FRAC,
                      "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                      "avg_launch_ms": main_ms, "flop_per_launch": flop_launch,
                      "window_samples_per_launch": window_samples,
@@ -437,10 +472,16 @@ def main(argv=None):
         log("serving leg: 2000 curves/s for 3 s")
         del flux, tim, trend
         torch.cuda.empty_cache()
-        out["serve"] = serve_sweep([2000.0], 3.0, args.budget_gb, log, check_oracle=False)["rates"][0]
+        # every 50th request is checked against the FP64 oracle after the run
+        out["serve"] = serve_sweep([2000.0], 3.0, args.budget_gb, log,
+                                   check_oracle=True)["rates"][0]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget)
+        if args.workload in (2, 3):
+            # the first 100 curves, extrapolated to the whole workload
+            out["cpu_baseline"] = cpu_baseline(batch, first_curves=100, total_windows=windows)
+        else:
+            out["cpu_baseline"] = cpu_baseline(batch, args.cpu_budget, total_windows=windows)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -74,9 +74,13 @@ typedef enum {
 /* Tuning knobs; zero in a field means "use the library's choice" (its
  * built-in defaults, or the tuning table loaded with umi_set_tuning).  With
  * tile = 0, a batch that the chosen tiles would cut into fewer tiles than the
- * device has compute units runs with tiles of at most 1024, then 512 output
- * positions, so that more of the chip shares it; results never depend on
- * the tiling. */
+ * device has compute units runs with tiles of at most 1024, 512, 256, 128,
+ * then 64 output positions, so that more of the chip shares it.  Tiles of
+ * more than 256 positions give each window one lane and results that do not
+ * depend on the tile size; tiles of at most 256 split every window over 2,
+ * 4 or 8 lanes (kept in step by cross-lane sums), which orders the sums
+ * differently: such results agree with the others to float32 rounding and
+ * are themselves deterministic. */
 typedef struct {
     int32_t mode;          /* umi_mode */
     int32_t tile;          /* output positions per tile (0 = auto) */
@@ -238,9 +242,15 @@ umi_status umi_plan_destroy(umi_plan* plan);
  * Returns -1 when either argument is not positive and finite. */
 int32_t umi_window_from_cadence(double cadence_days, double window_days);
 
-/* Tuning table: text lines "W_max tile groups_per_cu", sorted by W_max; a
- * batch curve uses the first line with W <= W_max.  NULL restores the
- * built-in defaults.  Returns UMI_ERR_INVALID_ARG on a malformed table. */
+/* Tuning table: text lines "W_max tile groups_per_cu [samples_max]".  A
+ * curve of a batch uses the first line with W <= W_max and, if samples_max
+ * is given and > 0, a batch of at most samples_max samples in total; lines
+ * are sorted by W_max, then by samples_max, with the lines for any batch
+ * size (no or 0 samples_max) last for their W_max.  A batch-size line fixes
+ * the tile (tiles of at most 256 positions split each window over 2, 4 or 8
+ * lanes); otherwise the small-batch rule of umi_launch applies.  NULL
+ * restores the built-in defaults.  Returns UMI_ERR_INVALID_ARG on a
+ * malformed table. */
 umi_status umi_set_tuning(const char* table_text);
 
 /* Thread-local message for the last non-OK status on this thread. */

@@ -1,11 +1,16 @@
-"""Autotuner for the persistent launch: tile size and workgroups per CU, per W bucket.
+"""Autotuner for the persistent launch: tile size (and with it the per-window
+work split) and workgroups per CU, per W bucket and batch-size bucket.
 
 For each window-size bucket the tuner times every candidate (tile, groups per
-CU) on a synthetic batch of that W with HIP events on the launch stream, keeps
-the fastest, and writes the winners as a tuning table -- the text format of
-``umi_set_tuning`` ("W_max tile groups_per_cu" per line) -- to a JSON cache
-keyed by GPU architecture and library version.  ``apply()`` loads the cached
-table for the current device into the library.
+CU) on a large synthetic batch of that W with HIP events on the launch stream
+and keeps the fastest; then, for batches of one, four and sixteen
+20,000-sample curves, it times tiles from the largest down to 64 positions
+(tiles of at most 256 positions split each window over 2, 4 or 8 lanes) and
+keeps the fastest call for each batch size.  The winners are written as a
+tuning table -- the text format of ``umi_set_tuning`` ("W_max tile
+groups_per_cu [samples_max]" per line) -- to a JSON cache keyed by GPU
+architecture and library version.  ``apply()`` loads the cached table for the
+current device into the library.
 
 Usage on a GPU:  python -m paper_2604_06602_amd.autotune [--out PATH]
 """
@@ -25,6 +30,11 @@ STAGE_MAX = 2048          # largest staged span (tile + W - 1) of the main kerne
 THREADS = 512             # threads per main-kernel workgroup
 BUCKETS = [(31, 25), (127, 121), (383, 361), (767, 721), (2047, 1441)]  # (W_max, W tried)
 GROUPS = [1, 2, 3, 4]
+SPLIT_TILES = [256, 128, 64]   # tiles that split a window over 2, 4 and 8 lanes
+# small batches (curves of SMALL_LENGTH samples): (curves, samples_max of the
+# tuning row it decides); larger batches take the bucket's general row
+SMALL_LENGTH = 20000
+SMALL_BATCHES = [(1, 40000), (4, 160000), (16, 640000)]
 
 
 MAX_TILE = 3 * THREADS    # at most three output positions per lane
@@ -50,6 +60,15 @@ def tile_candidates(W: int):
     c = {t for t in range(THREADS // 2, mt + 1, THREADS // 2)}
     c.add(mt)
     c.add(default_tile(W))
+    return sorted(c)
+
+
+def small_batch_candidates(W: int):
+    """Tiles for a batch too small to fill the GPU: the large-batch ones of at
+    least 512 positions and the split tiles."""
+    c = {t for t in tile_candidates(W) if t >= THREADS}
+    c.update(t for t in SPLIT_TILES if t <= max_tile(W))
+    c.add(max_tile(W))
     return sorted(c)
 
 
@@ -94,6 +113,22 @@ def tune(n_curves=400, length=20000, steps=5, log=print):
     rows, detail = [], {}
     _lib.set_tuning(None)
     for w_max, W in BUCKETS:
+        # small batches first: their rows precede the bucket's general row
+        for curves, samples_max in SMALL_BATCHES:
+            flux, time_, lengths, Ws = _workload(W, curves, SMALL_LENGTH, seed=curves)
+            trend = torch.empty_like(flux)
+            results = sorted((time_candidate(flux, time_, lengths, Ws, trend, tile, GROUPS[-1],
+                                             steps=max(steps, 20)), tile)
+                             for tile in small_batch_candidates(W))
+            rows.append((w_max, results[0][1], GROUPS[-1], samples_max))
+            detail["%d/%d" % (w_max, samples_max)] = {
+                "W": W, "curves": curves, "length": SMALL_LENGTH, "best_ms": results[0][0],
+                "candidates": [{"tile": t, "groups_per_cu": GROUPS[-1], "ms": m}
+                               for m, t in results]}
+            log("W<=%d (W=%d), %d curve(s) of %d: tile %d, %.3f ms per call (tile %d: %.3f ms)"
+                % (w_max, W, curves, SMALL_LENGTH, results[0][1], results[0][0],
+                   results[-1][1], results[-1][0]))
+            del flux, time_, trend
         flux, time_, lengths, Ws = _workload(W, n_curves, length)
         trend = torch.empty_like(flux)
         results = []
@@ -108,7 +143,7 @@ def tune(n_curves=400, length=20000, steps=5, log=print):
         default = [r for r in results if r[1] == default_tile(W) and r[2] == GROUPS[-1]]
         if default and default[0][0] <= best[0] * (1 + TIE):
             best = default[0]
-        rows.append((w_max, best[1], best[2]))
+        rows.append((w_max, best[1], best[2], 0))
         detail[str(w_max)] = {"W": W, "best_ms": best[0],
                               "candidates": [{"tile": t, "groups_per_cu": g, "ms": m}
                                              for m, t, g in results]}
@@ -116,7 +151,7 @@ def tune(n_curves=400, length=20000, steps=5, log=print):
             % (w_max, W, best[1], best[2], best[0], results[-1][0]))
         del flux, time_, trend
         torch.cuda.empty_cache()
-    table = "\n".join("%d %d %d" % r for r in rows) + "\n"
+    table = "".join("%d %d %d %d\n" % r if r[3] else "%d %d %d\n" % r[:3] for r in rows)
     return table, detail
 
 

@@ -27,11 +27,11 @@ namespace umi {
 
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
                           const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
-                          int4* segtab, int2* tiles, uint32_t* counter, hipStream_t stream);
-hipError_t launch_main(const float* flux, const int32_t* segid, const int4* segtab,
-                       const BatchHeader* hdr, const CurveDesc* curves, const int2* tiles,
-                       int tile_first, int tile_count, uint32_t* counter, int grid,
-                       float* trend, float* median, hipStream_t stream);
+                          int2* tiles, uint32_t* counter, hipStream_t stream);
+hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
+                       const CurveDesc* curves, const int2* tiles, int tile_first,
+                       int tile_count, uint32_t* counter, int grid, float* trend, float* median,
+                       hipStream_t stream);
 
 namespace {
 
@@ -61,10 +61,15 @@ bool take_injected(umi_status* s)
 // ---------------------------------------------------------------------------
 // tuning table: W_max -> (tile, groups per CU)
 
+// Tuning rows: for windows up to w_max and, when samples_max > 0, batches of
+// at most samples_max samples, a tile size and persistent workgroups per CU.
+// The table is sorted by w_max, then by samples_max with 0 ("any batch")
+// last within a w_max; a window takes the first row that matches.
 struct TuneRow {
     int w_max;
     int tile;
     int groups_per_cu;
+    int64_t samples_max;  // 0: any batch size
 };
 
 std::mutex g_tune_mu;
@@ -85,17 +90,21 @@ int default_tile(int W)
 }
 constexpr int kDefaultGroupsPerCU = 4;  // LDS (37.6 KB) allows four 512-thread groups per CU
 
-void tuned(int W, int* tile, int* gpc)
+// The tile and groups per CU for window W in a batch of `samples` samples
+// (< 0: any size).  `sized` tells whether a batch-size row chose them.
+void tuned(int W, int64_t samples, int* tile, int* gpc, bool* sized = nullptr)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     *tile = default_tile(W);
     *gpc = kDefaultGroupsPerCU;
+    if (sized) *sized = false;
     for (const TuneRow& r : g_tune) {
-        if (W <= r.w_max) {
-            if (r.tile > 0) *tile = std::min(r.tile, max_tile(W));
-            if (r.groups_per_cu > 0) *gpc = r.groups_per_cu;
-            break;
-        }
+        if (W > r.w_max) continue;
+        if (r.samples_max > 0 && (samples < 0 || samples > r.samples_max)) continue;
+        if (r.tile > 0) *tile = std::min(r.tile, max_tile(W));
+        if (r.groups_per_cu > 0) *gpc = r.groups_per_cu;
+        if (sized) *sized = r.samples_max > 0;
+        break;
     }
 }
 
@@ -161,8 +170,8 @@ umi_status check_curves(const int64_t* offsets, const int64_t* lengths, int64_t 
     ranges.reserve((size_t)n);
     for (int64_t b = 0; b < n; ++b) {
         if (lengths[b] < 0) return fail(UMI_ERR_INVALID_ARG, "curve lengths must be >= 0");
-        if (lengths[b] > (int64_t)INT32_MAX)
-            return fail(UMI_ERR_UNSUPPORTED, "a curve longer than 2^31-1 samples");
+        if (lengths[b] >= (int64_t)INT32_MAX)
+            return fail(UMI_ERR_UNSUPPORTED, "a curve of 2^31-1 samples or more");
         if (offsets[b] < 0 || offsets[b] > INT64_MAX - lengths[b])
             return fail(UMI_ERR_INVALID_ARG, "curve offsets must be >= 0");
         umi_status st = check_window(W[b]);
@@ -193,69 +202,86 @@ umi_status check_launch(const umi_launch* launch, umi_launch* opt)
 // ---------------------------------------------------------------------------
 // packer: the curve table in decreasing per-tile cost
 
-struct Packed {
-    std::vector<CurveDesc> curves;      // non-empty curves, cost order
-    std::vector<int64_t> curve_tiles;   // tiles per table entry
+// The packed curve table, written into caller-provided arrays of n_curves
+// entries (`tile_of` and `order` are scratch of the same length), so that a
+// caller can pack into memory it already holds.
+struct PackView {
+    CurveDesc* curves;        // non-empty curves, cost order
+    int64_t* curve_tiles;     // tiles per table entry
+    int* tile_of;             // scratch: tile size per input curve
+    int32_t* order;           // scratch: input index per table entry
+    int64_t ncurves = 0;      // entries written
     int64_t ntiles = 0;
-    int gpc = kDefaultGroupsPerCU;      // persistent groups per CU
+    int gpc = kDefaultGroupsPerCU;  // persistent groups per CU
 };
 
 // Tile sizes a batch too small to give every CU a tile falls back to, largest
-// first: at 512 each lane of a workgroup takes one window.
-constexpr int kSmallBatchTiles[] = {1024, 512};
+// first: at 512 each lane of a workgroup takes one window, at 256, 128 and 64
+// two, four and eight lanes share one.
+constexpr int kSmallBatchTiles[] = {1024, 512, 256, 128, 64};
 
-umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
-                float alpha, float c, const umi_options& o, const umi_launch& opt, int n_cu,
-                int64_t max_tiles, Packed* out)
+umi_status pack_into(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
+                     float alpha, float c, const umi_options& o, const umi_launch& opt, int n_cu,
+                     int64_t max_tiles, PackView* out)
 {
-    std::vector<int> tile_of((size_t)n);
-    std::vector<int32_t> order;
-    order.reserve((size_t)n);
+    int* tile_of = out->tile_of;
+    int32_t* order = out->order;
+    int64_t nord = 0, samples = 0;
+    for (int64_t b = 0; b < n; ++b) samples += std::max<int64_t>(lengths[b], 0);
+    bool any_sized = false;
     for (int64_t b = 0; b < n; ++b) {
         int t, g;
-        tuned(W[b], &t, &g);
+        bool sized;
+        tuned(W[b], samples, &t, &g, &sized);
+        any_sized = any_sized || sized;
         if (opt.tile > 0) t = std::min(opt.tile, max_tile(W[b]));
-        tile_of[(size_t)b] = t;
-        if (lengths[b] > 0) order.push_back((int32_t)b);
+        tile_of[b] = t;
+        if (lengths[b] > 0) order[nord++] = (int32_t)b;
     }
     // A batch that the tuned tiles cut into fewer tiles than there are CUs
     // (one curve, a quiet serving step) would leave most of the chip idle:
-    // smaller tiles spread its windows over more CUs.  Results do not depend
-    // on the tiling.  An explicit launch tile is kept as given.
+    // smaller tiles spread its windows over more CUs, down to tiles that
+    // split each window over 2, 4 or 8 lanes.  Tiles above kSplitMaxTile
+    // give identical results whatever their size; split tiles agree with them
+    // to rounding.  An explicit launch tile, or a tuning row for this batch
+    // size, is kept as given.
     auto count_tiles = [&](int cap) {
         int64_t t = 0;
-        for (int32_t b : order) {
-            const int tb = cap > 0 ? std::min(tile_of[(size_t)b], cap) : tile_of[(size_t)b];
+        for (int64_t i = 0; i < nord; ++i) {
+            const int32_t b = order[i];
+            const int tb = cap > 0 ? std::min(tile_of[b], cap) : tile_of[b];
             t += (lengths[b] + tb - 1) / tb;
         }
         return t;
     };
-    if (opt.tile == 0 && count_tiles(0) < n_cu) {
+    if (opt.tile == 0 && !any_sized && count_tiles(0) < n_cu) {
         for (int cap : kSmallBatchTiles) {
             if (count_tiles(cap) > max_tiles) break;
-            for (int32_t b : order) tile_of[(size_t)b] = std::min(tile_of[(size_t)b], cap);
+            for (int64_t i = 0; i < nord; ++i) tile_of[order[i]] = std::min(tile_of[order[i]], cap);
             if (count_tiles(0) >= n_cu) break;
         }
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const int64_t ca = (int64_t)W[a] * tile_of[(size_t)a];
-        const int64_t cb = (int64_t)W[b] * tile_of[(size_t)b];
+    // costliest tiles first; ties by length, then by input position (a total
+    // order, so std::sort needs no scratch and the table is deterministic)
+    std::sort(order, order + nord, [&](int32_t a, int32_t b) {
+        const int64_t ca = (int64_t)W[a] * tile_of[a];
+        const int64_t cb = (int64_t)W[b] * tile_of[b];
         if (ca != cb) return ca > cb;
-        return lengths[a] > lengths[b];
+        if (lengths[a] != lengths[b]) return lengths[a] > lengths[b];
+        return a < b;
     });
-    out->curves.resize(order.size());
-    out->curve_tiles.resize(order.size());
+    out->ncurves = nord;
     out->ntiles = 0;
-    for (size_t i = 0; i < order.size(); ++i) {
+    for (int64_t i = 0; i < nord; ++i) {
         const int32_t b = order[i];
-        const int64_t nt = (lengths[b] + tile_of[(size_t)b] - 1) / tile_of[(size_t)b];
+        const int64_t nt = (lengths[b] + tile_of[b] - 1) / tile_of[b];
         if (out->ntiles + nt > (int64_t)INT32_MAX)
             return fail(UMI_ERR_UNSUPPORTED, "too many tiles in one batch");
         CurveDesc& d = out->curves[i];
         d.off = offsets[b];
         d.len = (int32_t)lengths[b];
         d.W = W[b];
-        d.tile = tile_of[(size_t)b];
+        d.tile = tile_of[b];
         d.tile_base = (int32_t)out->ntiles;
         d.alpha = o.alpha ? o.alpha[b] : alpha;
         d.c = o.c ? o.c[b] : c;
@@ -264,11 +290,37 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
         out->ntiles += nt;
     }
     out->gpc = kDefaultGroupsPerCU;
-    if (!order.empty()) {
+    if (nord > 0) {
         int t_unused;
-        tuned(W[order[0]], &t_unused, &out->gpc);  // the costliest curve's row
+        tuned(W[order[0]], samples, &t_unused, &out->gpc);  // the costliest curve's row
     }
     if (opt.groups_per_cu > 0) out->gpc = opt.groups_per_cu;
+    return UMI_OK;
+}
+
+// The allocating calls' packer: the same table in vectors.
+struct Packed {
+    std::vector<CurveDesc> curves;
+    std::vector<int64_t> curve_tiles;
+    int64_t ntiles = 0;
+    int gpc = kDefaultGroupsPerCU;
+};
+
+umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
+                float alpha, float c, const umi_options& o, const umi_launch& opt, int n_cu,
+                int64_t max_tiles, Packed* out)
+{
+    std::vector<int> tile_of((size_t)n);
+    std::vector<int32_t> order((size_t)n);
+    out->curves.resize((size_t)n);
+    out->curve_tiles.resize((size_t)n);
+    PackView v{out->curves.data(), out->curve_tiles.data(), tile_of.data(), order.data()};
+    umi_status st = pack_into(offsets, lengths, n, W, alpha, c, o, opt, n_cu, max_tiles, &v);
+    if (st != UMI_OK) return st;
+    out->curves.resize((size_t)v.ncurves);
+    out->curve_tiles.resize((size_t)v.ncurves);
+    out->ntiles = v.ntiles;
+    out->gpc = v.gpc;
     return UMI_OK;
 }
 
@@ -277,26 +329,28 @@ size_t block_bytes(int64_t ncurves)
     return sizeof(BatchHeader) + (size_t)ncurves * sizeof(CurveDesc);
 }
 
-void write_block(uint8_t* dst, const Packed& p, int32_t iters, const umi_options& o,
-                 const double* time)
+void write_block(uint8_t* dst, const CurveDesc* curves, int64_t ncurves, int64_t ntiles,
+                 int32_t iters, const umi_options& o, const double* time)
 {
     BatchHeader h = {};
-    h.n_curves = (int32_t)p.curves.size();
-    h.n_tiles = (int32_t)p.ntiles;
+    h.n_curves = (int32_t)ncurves;
+    h.n_tiles = (int32_t)ntiles;
     h.iters = iters;
     h.scale = o.scale;
     h.detrended = o.detrended;
     h.time = time;
     std::memcpy(dst, &h, sizeof h);
-    if (!p.curves.empty())
-        std::memcpy(dst + sizeof h, p.curves.data(), p.curves.size() * sizeof(CurveDesc));
+    if (ncurves > 0) std::memcpy(dst + sizeof h, curves, (size_t)ncurves * sizeof(CurveDesc));
 }
 
 // ---------------------------------------------------------------------------
 // device buffers of a launch sequence
 
+// Grows `*p` to hold `need` elements.  The direct calls keep a quarter of
+// slack so that batches of slowly growing size do not reallocate every call;
+// a plan reserves exactly its fixed capacity once (`exact`).
 template <class T>
-hipError_t grow(T** p, int64_t* cap, int64_t need)
+hipError_t grow(T** p, int64_t* cap, int64_t need, bool exact = false)
 {
     if (need <= *cap) return hipSuccess;
     if (*p) {
@@ -305,38 +359,40 @@ hipError_t grow(T** p, int64_t* cap, int64_t need)
         *cap = 0;
         if (e != hipSuccess) return e;
     }
-    int64_t n = std::max<int64_t>(need + need / 4, 1024);
+    int64_t n = exact ? std::max<int64_t>(need, 1) : std::max<int64_t>(need + need / 4, 1024);
     hipError_t e = hipMalloc(reinterpret_cast<void**>(p), (size_t)n * sizeof(T));
     if (e == hipSuccess) *cap = n;
     return e;
 }
 
 struct DeviceBuffers {
-    int32_t* segid = nullptr;   // per sample slot
+    int32_t* segid = nullptr;   // per sample slot: the segment word of each sample
     int64_t cap_segid = 0;
-    int4* segtab = nullptr;     // per sample slot (used per segment)
-    int64_t cap_segtab = 0;
     int2* tiles = nullptr;
     int64_t cap_tiles = 0;
     uint32_t* counter = nullptr;
     int64_t cap_counter = 0;
 
-    hipError_t reserve(int64_t span, int64_t ntiles)
+    hipError_t reserve(int64_t span, int64_t ntiles, bool exact = false)
     {
         hipError_t e;
-        if ((e = grow(&segid, &cap_segid, span)) != hipSuccess) return e;
-        if ((e = grow(&segtab, &cap_segtab, span)) != hipSuccess) return e;
-        if ((e = grow(&tiles, &cap_tiles, ntiles)) != hipSuccess) return e;
-        return grow(&counter, &cap_counter, 1);
+        if ((e = grow(&segid, &cap_segid, span, exact)) != hipSuccess) return e;
+        if ((e = grow(&tiles, &cap_tiles, ntiles, exact)) != hipSuccess) return e;
+        return grow(&counter, &cap_counter, 1, exact);
     }
     bool fits(int64_t span, int64_t ntiles) const
     {
-        return span <= cap_segid && span <= cap_segtab && ntiles <= cap_tiles && cap_counter >= 1;
+        return span <= cap_segid && ntiles <= cap_tiles && cap_counter >= 1;
+    }
+    // device bytes held
+    int64_t bytes() const
+    {
+        return cap_segid * (int64_t)sizeof(int32_t) + cap_tiles * (int64_t)sizeof(int2) +
+               cap_counter * (int64_t)sizeof(uint32_t);
     }
     void release()
     {
         if (segid) (void)hipFree(segid);
-        if (segtab) (void)hipFree(segtab);
         if (tiles) (void)hipFree(tiles);
         if (counter) (void)hipFree(counter);
         *this = DeviceBuffers();
@@ -345,34 +401,36 @@ struct DeviceBuffers {
 
 // Enqueue the pre-pass and estimate kernels for a staged block (header +
 // curve table, at `dblock` on the device by the time the stream reaches them).
+// In per-curve mode `table` and `curve_tiles` (host copies of the staged
+// table) give each curve's tile range.
 hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, float* median,
                            const uint8_t* dblock, const DeviceBuffers& b, int mode,
-                           const Packed* p, int prep_grid, int main_grid, hipEvent_t ev0,
-                           hipEvent_t ev1, hipStream_t stream)
+                           const CurveDesc* table, const int64_t* curve_tiles, int prep_grid,
+                           int main_grid, hipEvent_t ev0, hipEvent_t ev1, hipStream_t stream)
 {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblock);
     const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
     hipError_t e;
     if (mode == UMI_MODE_PERSISTENT) {
-        if ((e = launch_prepass(flux, time, hdr, curves, 0, prep_grid, b.segid, b.segtab, b.tiles,
+        if ((e = launch_prepass(flux, time, hdr, curves, 0, prep_grid, b.segid, b.tiles,
                                 b.counter, stream)) != hipSuccess)
             return e;
         if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
-        if ((e = launch_main(flux, b.segid, b.segtab, hdr, curves, b.tiles, 0, -1, b.counter,
-                             main_grid, trend, median, stream)) != hipSuccess)
+        if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, 0, -1, b.counter, main_grid,
+                             trend, median, stream)) != hipSuccess)
             return e;
         if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
         return hipSuccess;
     }
     // one pre-pass and one estimate launch per curve, one workgroup per tile
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
-    for (size_t i = 0; i < p->curves.size(); ++i) {
-        if ((e = launch_prepass(flux, time, hdr, curves, (int)i, 1, b.segid, b.segtab, b.tiles,
-                                nullptr, stream)) != hipSuccess)
+    for (int i = 0; i < prep_grid; ++i) {
+        if ((e = launch_prepass(flux, time, hdr, curves, i, 1, b.segid, b.tiles, nullptr,
+                                stream)) != hipSuccess)
             return e;
-        const int nt = (int)p->curve_tiles[i];
-        if ((e = launch_main(flux, b.segid, b.segtab, hdr, curves, b.tiles,
-                             p->curves[i].tile_base, nt, nullptr, nt, trend, median, stream)) !=
+        const int nt = (int)curve_tiles[i];
+        if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, table[i].tile_base, nt, nullptr,
+                             nt, trend, median, stream)) !=
             hipSuccess)
             return e;
     }
@@ -508,7 +566,7 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
             return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
-    write_block(ws->hblock, p, iters, o, time);
+    write_block(ws->hblock, p.curves.data(), nc, p.ntiles, iters, o, time);
     if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return fail_hip(e, "curve table copy");
@@ -516,8 +574,9 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
         return fail_hip(e, "hipEventRecord");
     ws->staged_pending = true;
     const int grid = (int)std::min<int64_t>(p.ntiles, (int64_t)p.gpc * cu_count(device));
-    e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, &p, (int)nc,
-                        grid, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
+    e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, p.curves.data(),
+                        p.curve_tiles.data(), (int)nc, grid, (hipEvent_t)opt.main_start,
+                        (hipEvent_t)opt.main_stop, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -637,11 +696,14 @@ struct umi_plan {
     float* median = nullptr;
     int main_grid = 0;
     umi::DeviceBuffers buf;
+    // Two captured graphs per slot: [0] for batches of at most
+    // kPrepWideCurves curves (a pre-pass grid of that many wide workgroups,
+    // and a copy of that much of the table), [1] for up to max_curves.
     struct Slot {
         uint8_t* host = nullptr;    // pinned header + curve table
         uint8_t* dev = nullptr;     // its device copy
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph[2] = {nullptr, nullptr};
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
         hipEvent_t done = nullptr;  // recorded after the slot's last replay
         bool pending = false;
     } slot[2];
@@ -654,8 +716,10 @@ namespace {
 void plan_free(umi_plan* p)
 {
     for (auto& s : p->slot) {
-        if (s.exec) (void)hipGraphExecDestroy(s.exec);
-        if (s.graph) (void)hipGraphDestroy(s.graph);
+        for (int k = 0; k < 2; ++k) {
+            if (s.exec[k]) (void)hipGraphExecDestroy(s.exec[k]);
+            if (s.graph[k]) (void)hipGraphDestroy(s.graph[k]);
+        }
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
@@ -745,17 +809,35 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
     if (!flux || !trend) return umi::fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
     if (!stream)
         return umi::fail(UMI_ERR_INVALID_ARG, "plans need a non-default stream (graph capture)");
-    // the smallest tile any W <= max_W may use, with or without tuning
+    int device = 0;
+    hipError_t de = hipGetDevice(&device);
+    if (de != hipSuccess) return umi::fail_hip(de, "hipGetDevice");
+    const int64_t n_cu = umi::cu_count(device);
+    // Tiles the plan must hold: the whole capacity at the smallest tile any
+    // W <= max_W takes for batches of any size; batches at most samples_max
+    // long at their batch-size rows' tiles; and the small-batch rule, which
+    // only halves tiles while a batch has fewer tiles than CUs, so it never
+    // needs more than 2 n_cu + max_curves.  With room for all of these, a run
+    // is cut exactly as the direct calls cut the same batch.
     int64_t min_tile = std::min(umi::max_tile(max_W), umi::default_tile(max_W));
+    int64_t sized_tiles = 0;
     {
         std::lock_guard<std::mutex> lk(umi::g_tune_mu);
-        for (const umi::TuneRow& r : umi::g_tune)
-            if (r.tile > 0) min_tile = std::min<int64_t>(min_tile, r.tile);
+        for (const umi::TuneRow& r : umi::g_tune) {
+            if (r.tile <= 0) continue;
+            const int64_t t = std::min<int64_t>(r.tile, umi::max_tile(std::min(r.w_max, (int)max_W)));
+            if (r.samples_max == 0)
+                min_tile = std::min<int64_t>(min_tile, t);
+            else
+                sized_tiles = std::max(sized_tiles, std::min(r.samples_max, capacity) / t + 1);
+        }
     }
-    const int64_t max_tiles = capacity / std::max<int64_t>(1, min_tile) + max_curves;
+    const int64_t max_tiles = std::max(capacity / std::max<int64_t>(1, min_tile),
+                                       std::max(sized_tiles, 2 * n_cu)) + max_curves;
     if (max_tiles > (int64_t)INT32_MAX)
         return umi::fail(UMI_ERR_UNSUPPORTED, "plan capacity needs too many tiles");
     umi_plan* p = new umi_plan();
+    p->device = device;
     p->stream = static_cast<hipStream_t>(stream);
     p->capacity = capacity;
     p->max_curves = max_curves;
@@ -765,8 +847,7 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
     p->time = time;
     p->trend = trend;
     p->median = median;
-    hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess) e = p->buf.reserve(capacity, max_tiles);
+    hipError_t e = p->buf.reserve(capacity, max_tiles, /*exact=*/true);
     const size_t bytes = umi::block_bytes(max_curves);
     for (auto& s : p->slot) {
         if (e == hipSuccess)
@@ -781,7 +862,7 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
         return umi::fail_hip(e, "plan allocation");
     }
     int t_unused, gpc;
-    umi::tuned(max_W, &t_unused, &gpc);
+    umi::tuned(max_W, -1, &t_unused, &gpc);
     p->main_grid = gpc * umi::cu_count(p->device);
     *out = p;
     return UMI_OK;
@@ -826,17 +907,23 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
             return umi::fail_hip(e, "hipEventSynchronize");
         s.pending = false;
     }
-    umi::write_block(s.host, pk, iters, o, p->time);
-    if (!s.exec) {
-        // capture once per slot: copy of the staged block, pre-pass over
-        // max_curves (blocks beyond the batch exit), persistent estimate
+    umi::write_block(s.host, pk.curves.data(), (int64_t)pk.curves.size(), pk.ntiles, iters, o,
+                     p->time);
+    // few curves: the wide pre-pass over kPrepWideCurves workgroups instead
+    // of one narrow workgroup per possible curve
+    const int kind = (int64_t)pk.curves.size() <= umi::kPrepWideCurves ? 0 : 1;
+    const int64_t cap_curves =
+        kind == 0 ? std::min<int64_t>(p->max_curves, umi::kPrepWideCurves) : p->max_curves;
+    if (!s.exec[kind]) {
+        // capture once per slot and kind: copy of the staged block, pre-pass
+        // over cap_curves (blocks beyond the batch exit), persistent estimate
         if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return umi::fail_hip(e, "hipStreamBeginCapture");
-        hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(p->max_curves),
+        hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(cap_curves),
                                        hipMemcpyHostToDevice, p->stream);
         if (ce == hipSuccess)
             ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
-                                      UMI_MODE_PERSISTENT, nullptr, (int)p->max_curves,
+                                      UMI_MODE_PERSISTENT, nullptr, nullptr, (int)cap_curves,
                                       p->main_grid, nullptr, nullptr, p->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->stream, &g);
@@ -844,13 +931,13 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
             if (g) (void)hipGraphDestroy(g);
             return umi::fail_hip(ce != hipSuccess ? ce : e, "graph capture");
         }
-        s.graph = g;
-        if ((e = hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0)) != hipSuccess) {
-            s.exec = nullptr;
+        s.graph[kind] = g;
+        if ((e = hipGraphInstantiate(&s.exec[kind], g, nullptr, nullptr, 0)) != hipSuccess) {
+            s.exec[kind] = nullptr;
             return umi::fail_hip(e, "hipGraphInstantiate");
         }
     }
-    if ((e = hipGraphLaunch(s.exec, p->stream)) != hipSuccess)
+    if ((e = hipGraphLaunch(s.exec[kind], p->stream)) != hipSuccess)
         return umi::fail_hip(e, "hipGraphLaunch");
     if ((e = hipEventRecord(s.done, p->stream)) != hipSuccess)
         return umi::fail_hip(e, "hipEventRecord");
@@ -897,17 +984,33 @@ umi_status umi_set_tuning(const char* table_text)
             if (line.find_first_not_of(" \t\r") == std::string::npos) continue;  // blank
             std::istringstream ls(line);
             umi::TuneRow r;
+            r.samples_max = 0;
             if (!(ls >> r.w_max >> r.tile >> r.groups_per_cu) || r.w_max < 1 || r.tile < 0 ||
                 r.groups_per_cu < 0 || r.groups_per_cu > 64)
                 return umi::fail(UMI_ERR_INVALID_ARG, "malformed tuning line: " + line);
             std::string extra;
-            if (ls >> extra) return umi::fail(UMI_ERR_INVALID_ARG, "malformed tuning line: " + line);
+            if (ls >> extra) {  // optional fourth column: batch samples bound
+                char* end = nullptr;
+                const long long v = std::strtoll(extra.c_str(), &end, 10);
+                std::string more;
+                if (end == extra.c_str() || *end != '\0' || v < 0 || (ls >> more))
+                    return umi::fail(UMI_ERR_INVALID_ARG, "malformed tuning line: " + line);
+                r.samples_max = v;
+            }
             rows.push_back(r);
         }
+        auto after = [](const umi::TuneRow& a, const umi::TuneRow& b) {
+            // b may follow a: larger w_max, or the same w_max with a larger
+            // batch bound (0, any size, last)
+            if (b.w_max != a.w_max) return b.w_max > a.w_max;
+            if (a.samples_max == 0) return false;
+            return b.samples_max == 0 || b.samples_max > a.samples_max;
+        };
         for (size_t i = 1; i < rows.size(); ++i)
-            if (rows[i].w_max <= rows[i - 1].w_max)
+            if (!after(rows[i - 1], rows[i]))
                 return umi::fail(UMI_ERR_INVALID_ARG,
-                                 "tuning rows must be sorted by increasing W_max");
+                                 "tuning rows must be sorted by W_max, then by batch samples "
+                                 "(0 = any size, last)");
     }
     std::lock_guard<std::mutex> lk(umi::g_tune_mu);
     umi::g_tune = rows;
@@ -932,7 +1035,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.6.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.7.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

@@ -13,10 +13,20 @@ constexpr int kStageLog2 = 11;
 constexpr int kWords = kStageMax / 64 + 1;  // bit-vector words incl. sentinel
 constexpr int kMainThreads = 512;            // threads per main-kernel workgroup
 constexpr int kMaxTile = 3 * kMainThreads;   // output positions per tile: <= 3 per lane
+constexpr int kSplitMaxTile = kMainThreads / 2;  // tiles this small split windows
+
+// Lanes that share one window for a tile of `tile` output positions: 1 above
+// kSplitMaxTile (each lane takes up to three windows), else the largest of 2,
+// 4, 8 with tile * G <= kMainThreads.
+__host__ __device__ constexpr int split_lanes(int tile)
+{
+    return tile > kSplitMaxTile ? 1 : (tile > kMainThreads / 4 ? 2 : (tile > kMainThreads / 8 ? 4 : 8));
+}
 constexpr int kPrepThreads = 256;            // threads per pre-pass workgroup
 constexpr int kPrepWideThreads = 1024;       // ... when a launch covers few curves
 constexpr int kPrepWideCurves = 64;          // "few": at most this many
 constexpr int kPrepItems = 4;                // samples per pre-pass thread per chunk
+constexpr int kPrepWideItems = 8;            // ... in the 1024-thread workgroups
 constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1
 constexpr double kGapDays = 0.5;             // segment break threshold (days)
 
@@ -46,10 +56,13 @@ struct CurveDesc {
 };
 static_assert(sizeof(CurveDesc) == 40, "CurveDesc layout");
 
-// Segment record written by the pre-pass at segtab[curve.off + segment id]:
-//   x = first valid index, y = last valid index (curve-local),
-//   z = valid samples before the segment, w = valid samples through its end.
-// A segment is live when w - z >= max(1, W / 3).
+// Per-sample segment word written by the pre-pass at segid[curve.off + i]:
+//   -1       sample i is invalid;
+//   x >= 0   sample i is valid and its segment starts at the valid sample x
+//            (curve-local index, x < i);
+//   -2 - n   sample i is valid and starts a segment of n valid samples.
+// A segment is live when n >= max(1, W / 3).  Curves hold fewer than
+// 2^31 - 1 samples, so -2 - n never overflows.
 
 // Tile record written by the pre-pass: x = index into the curve table,
 // y = first output position (curve-local).

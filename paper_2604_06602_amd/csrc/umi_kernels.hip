@@ -60,56 +60,77 @@ __device__ __forceinline__ int wave_incl_sum(int x)
     return x;
 }
 
-// Inclusive "latest valid sample" scan: the largest index seen so far (-1 if
-// none) together with its time.
-__device__ __forceinline__ void wave_incl_latest(int& idx, double& t)
+// Inclusive "latest" scan over the lanes of a wave: the pair (idx, val) of
+// the highest lane so far whose idx is >= 0 (idx grows with the lane where
+// set, so the latest is the largest).
+__device__ __forceinline__ void wave_incl_latest(int& idx, int& val)
 {
     const int lane = __lane_id();
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        int yi = __shfl_up(idx, d, 64);
-        double yt = __shfl_up(t, d, 64);
+        const int yi = __shfl_up(idx, d, 64);
+        const int yv = __shfl_up(val, d, 64);
         if (lane >= d && yi > idx) {
             idx = yi;
-            t = yt;
+            val = yv;
         }
     }
 }
 
-// Exclusive block-wide sum over NT threads; `total` gets the sum.
-template <int NT>
-__device__ __forceinline__ int block_excl_sum(int x, int* sh, int& total)
+// The same for an (index, time) pair, together with an inclusive sum `cnt`.
+template <class T>
+__device__ __forceinline__ void wave_incl_latest_sum(int& idx, T& val, int& cnt)
 {
-    const int incl = wave_incl_sum(x);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) sh[w] = incl;
-    __syncthreads();
-    int before = 0, tot = 0;
+    const int lane = __lane_id();
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) {
-        int v = sh[i];
-        before += (i < w) ? v : 0;
-        tot += v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int yi = __shfl_up(idx, d, 64);
+        const T yv = __shfl_up(val, d, 64);
+        const int yc = __shfl_up(cnt, d, 64);
+        if (lane >= d) {
+            if (yi > idx) {
+                idx = yi;
+                val = yv;
+            }
+            cnt += yc;
+        }
     }
-    __syncthreads();
-    total = tot;
-    return before + incl - x;
 }
 
 // ---------------------------------------------------------------------------
 // Pre-pass: segments and tiles.
+//
+// One workgroup walks one curve in chunks of NT * K samples (K consecutive
+// samples per thread).  It writes one int32 per sample:
+//   -1                    the sample is invalid (non-finite flux or time);
+//   x >= 0                a valid sample whose segment starts at the valid
+//                         sample x (curve-local index), x < this sample;
+//   -2 - n  (<= -2)       the first valid sample of a segment of n valid
+//                         samples (the segment's record lives in its first
+//                         slot, so the workspace is 4 bytes per sample).
+// A new segment starts at a valid sample whose predecessor among valid
+// samples is more than kGapDays earlier (strictly), and at the first valid
+// sample.  The slot of a segment's first sample is written once, by whoever
+// sees the segment end (the thread holding the next start, or thread 0 at the
+// end of the curve), so no slot has two writers.  The scans per chunk: the
+// latest valid sample (index, time) with the valid count, then the latest
+// segment start (index, valid count before it); chunk carries make them
+// curve-wide.  Two barriers per chunk: each LDS array is written in one phase
+// and read in the next, and a phase's writes follow the barrier that ends
+// every wave's reads of the same array in the chunk before.
 
-template <int NT>
+template <int NT, int K>
 __global__ __launch_bounds__(NT) void umi_prepass_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
     const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_first,
-    int32_t* __restrict__ segid, int4* __restrict__ segtab,
-    int2* __restrict__ tiles, uint32_t* __restrict__ counter)
+    int32_t* __restrict__ segid, int2* __restrict__ tiles, uint32_t* __restrict__ counter)
 {
-    __shared__ int sh_li[NT / 64];
-    __shared__ double sh_lt[NT / 64];
-    __shared__ int sh_a[NT / 64];
-    __shared__ int sh_b[NT / 64];
+    constexpr int NW = NT / 64;
+    __shared__ int sh_vi[NW];      // per wave: latest valid index
+    __shared__ double sh_vt[NW];   //           its time
+    __shared__ int sh_vc[NW];      //           valid count
+    __shared__ int sh_sx[NW];      // per wave: latest segment start
+    __shared__ int sh_sz[NW];      //           valid samples before it
 
     if (counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
     const int cidx = curve_first + (int)blockIdx.x;
@@ -123,26 +144,26 @@ __global__ __launch_bounds__(NT) void umi_prepass_kernel(
     const float* f = flux + cd.off;
     const double* tm = time ? time + cd.off : nullptr;
     int32_t* sid = segid + cd.off;
-    int* tab = reinterpret_cast<int*>(segtab + cd.off);
 
     // carries from earlier chunks (uniform over the block)
-    int c_idx = -1;    // latest valid index
-    double c_t = 0.0;  // its time
-    int c_vc = 0;      // valid samples so far
-    int c_ns = 0;      // segments so far
+    int c_vi = -1;      // latest valid index
+    double c_vt = 0.0;  // its time
+    int c_vc = 0;       // valid samples so far
+    int c_sx = -1;      // latest segment start
+    int c_sz = 0;       // valid samples before it
 
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
-    constexpr int kChunk = NT * kPrepItems;
+    constexpr int kChunk = NT * K;
 
     // The next chunk's flux and times are loaded while the current one is
-    // scanned, so the loads' latency overlaps the block scans.
-    float fv[kPrepItems];
-    double tv[kPrepItems];
+    // scanned, so the loads' latency overlaps the scans.
+    float fv[K];
+    double tv[K];
     auto load_chunk = [&](int base, float* fo, double* to) {
 #pragma unroll
-        for (int q = 0; q < kPrepItems; ++q) {
-            const int e = base + (int)threadIdx.x * kPrepItems + q;
+        for (int q = 0; q < K; ++q) {
+            const int e = base + (int)threadIdx.x * K + q;
             fo[q] = e < cd.len ? f[e] : __builtin_nanf("");
             to[q] = (tm != nullptr && e < cd.len) ? tm[e] : 0.0;
         }
@@ -150,125 +171,137 @@ __global__ __launch_bounds__(NT) void umi_prepass_kernel(
     load_chunk(0, fv, tv);
 
     for (int base = 0; base < cd.len; base += kChunk) {
-        float nf[kPrepItems];
-        double nt[kPrepItems];
+        float nf[K];
+        double nt[K];
         if (base + kChunk < cd.len) load_chunk(base + kChunk, nf, nt);
-        const int e0 = base + (int)threadIdx.x * kPrepItems;
+        const int e0 = base + (int)threadIdx.x * K;
         uint32_t vmask = 0;  // bit q: item q is valid
-        double t[kPrepItems];
-        int a_idx = -1, a_cnt = 0;
-        double a_t = 0.0;
+        int vi = -1, vc = 0;
+        double vt = 0.0;
 #pragma unroll
-        for (int q = 0; q < kPrepItems; ++q) {
-            const int e = e0 + q;
-            const bool ok = e < cd.len && isfinite(fv[q]) && (tm == nullptr || isfinite(tv[q]));
+        for (int q = 0; q < K; ++q) {
+            const bool ok = e0 + q < cd.len && isfinite(fv[q]) && (tm == nullptr || isfinite(tv[q]));
             vmask |= (ok ? 1u : 0u) << q;
-            t[q] = tv[q];
             if (ok) {
-                a_idx = e;
-                a_t = tv[q];
-                ++a_cnt;
+                vi = e0 + q;
+                vt = tv[q];
+                ++vc;
             }
         }
 
-        // latest valid sample before this thread's items, and valid count
-        int li = a_idx;
-        double lt = a_t;
-        wave_incl_latest(li, lt);
-        int ex_i = __shfl_up(li, 1, 64);
-        double ex_t = __shfl_up(lt, 1, 64);
-        if (lane == 0) {
-            ex_i = -1;
-            ex_t = 0.0;
-        }
+        // phase 1: latest valid sample and valid count before this thread's items
+        const int own_vc = vc;
+        wave_incl_latest_sum(vi, vt, vc);
         if (lane == 63) {
-            sh_li[w] = li;
-            sh_lt[w] = lt;
+            sh_vi[w] = vi;
+            sh_vt[w] = vt;
+            sh_vc[w] = vc;
         }
-        int tot_cnt;
-        const int ex_cnt = block_excl_sum<NT>(a_cnt, sh_a, tot_cnt);  // syncs
-        int blk_i = -1;
-        double blk_t = 0.0;
-        for (int i = 0; i < NT / 64; ++i) {
-            const int wi = sh_li[i];
-            if (wi > blk_i) {
-                blk_i = wi;
-                blk_t = sh_lt[i];
-            }
-            if (i + 1 == w && ex_i < 0) {
-                // nothing earlier in this wave: take the lower waves' latest
+        int ex_i = __shfl_up(vi, 1, 64);
+        double ex_t = __shfl_up(vt, 1, 64);
+        int before = vc - own_vc;  // valid samples earlier in this wave
+        if (lane == 0) ex_i = -1;
+        __syncthreads();
+        int blk_i = c_vi, tot = 0;
+        double blk_t = c_vt;
+        for (int i = 0; i < NW; ++i) {
+            if (i == w && ex_i < 0) {  // nothing valid earlier in this wave
                 ex_i = blk_i;
                 ex_t = blk_t;
             }
+            if (i < w) before += sh_vc[i];
+            tot += sh_vc[i];
+            if (sh_vi[i] >= 0) {
+                blk_i = sh_vi[i];
+                blk_t = sh_vt[i];
+            }
         }
-        if (ex_i < 0) {
-            ex_i = c_idx;
-            ex_t = c_t;
-        }
+        before += c_vc;
 
-        // segment starts among this thread's items
-        uint32_t smask = 0;  // bit q: item q starts a segment
-        int n_st = 0;
+        // phase 2: segment starts among this thread's items, then the latest
+        // start before them
+        int sx = -1, sz = 0;
         {
             int pi = ex_i;
             double pt = ex_t;
+            int v = before;
 #pragma unroll
-            for (int q = 0; q < kPrepItems; ++q) {
+            for (int q = 0; q < K; ++q) {
                 if ((vmask >> q) & 1u) {
-                    const bool st = (pi < 0) || (tm != nullptr && (t[q] - pt) > kGapDays);
-                    smask |= (st ? 1u : 0u) << q;
-                    n_st += st ? 1 : 0;
+                    if (pi < 0 || (tm != nullptr && (tv[q] - pt) > kGapDays)) {
+                        sx = e0 + q;
+                        sz = v;
+                    }
                     pi = e0 + q;
-                    pt = t[q];
+                    pt = tv[q];
+                    ++v;
                 }
             }
         }
-        int tot_st;
-        const int ex_st = block_excl_sum<NT>(n_st, sh_b, tot_st);  // syncs
+        wave_incl_latest(sx, sz);
+        if (lane == 63) {
+            sh_sx[w] = sx;
+            sh_sz[w] = sz;
+        }
+        int px = __shfl_up(sx, 1, 64);
+        int pz = __shfl_up(sz, 1, 64);
+        if (lane == 0) px = -1;
+        __syncthreads();
         {
-            int s = c_ns + ex_st - 1;
-            int pi = ex_i;               // previous valid index
-            int vc = c_vc + ex_cnt;      // valid samples before item q
+            int bx = c_sx, bz = c_sz;
+            for (int i = 0; i < NW; ++i) {
+                if (i == w && px < 0) {
+                    px = bx;
+                    pz = bz;
+                }
+                if (sh_sx[i] >= 0) {
+                    bx = sh_sx[i];
+                    bz = sh_sz[i];
+                }
+            }
+            // every wave has read the phase-1 arrays; carries for the next chunk
+            if (blk_i >= 0) {
+                c_vi = blk_i;
+                c_vt = blk_t;
+            }
+            c_vc += tot;
+            c_sx = bx;
+            c_sz = bz;
+        }
+
+        // writes: segment of each item; a start closes the segment before it
+        {
+            int pi = ex_i;
+            double pt = ex_t;
+            int v = before;
 #pragma unroll
-            for (int q = 0; q < kPrepItems; ++q) {
+            for (int q = 0; q < K; ++q) {
                 const int e = e0 + q;
                 if (e < cd.len) {
                     if ((vmask >> q) & 1u) {
-                        if ((smask >> q) & 1u) {
-                            ++s;
-                            tab[4 * s + 0] = e;
-                            tab[4 * s + 2] = vc;
-                            if (s > 0) {
-                                tab[4 * (s - 1) + 1] = pi;
-                                tab[4 * (s - 1) + 3] = vc;
-                            }
+                        if (pi < 0 || (tm != nullptr && (tv[q] - pt) > kGapDays)) {
+                            if (px >= 0) sid[px] = -2 - (v - pz);
+                            px = e;
+                            pz = v;
+                        } else {
+                            sid[e] = px;
                         }
-                        sid[e] = s;
                         pi = e;
-                        ++vc;
+                        pt = tv[q];
+                        ++v;
                     } else {
                         sid[e] = -1;
                     }
                 }
             }
         }
-        if (blk_i >= 0) {
-            c_idx = blk_i;
-            c_t = blk_t;
-        }
-        c_vc += tot_cnt;
-        c_ns += tot_st;
 #pragma unroll
-        for (int q = 0; q < kPrepItems; ++q) {
+        for (int q = 0; q < K; ++q) {
             fv[q] = nf[q];
             tv[q] = nt[q];
         }
-        __syncthreads();  // sh_li / sh_lt reused by the next chunk
     }
-    if (threadIdx.x == 0 && c_ns > 0) {
-        tab[4 * (c_ns - 1) + 1] = c_idx;
-        tab[4 * (c_ns - 1) + 3] = c_vc;
-    }
+    if (threadIdx.x == 0 && c_sx >= 0) sid[c_sx] = -2 - (c_vc - c_sz);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,6 +329,7 @@ struct MainSmem {
     uint32_t zeros[kStageLog2];           // zeros per level
     uint64_t vbits[kWords];               // staged-sample validity
     uint32_t vpre[kWords];
+    uint64_t sbits[kWords];               // staged samples that start a segment
     int tile;
     int nvalid;
 };
@@ -613,12 +647,107 @@ __device__ __forceinline__ void small_window_medians(const uint32_t* __restrict_
     }
 }
 
+// The window of output position p: its valid samples are the compacted
+// positions [ca, ca + n) of the staged tile.  False when p is invalid or in a
+// dead segment (a NaN output).
+__device__ __forceinline__ bool window_range(const MainSmem& sm, const CurveDesc& cd,
+                                             const int32_t* __restrict__ segid,
+                                             const double* __restrict__ time, int h, int s0,
+                                             int N, int m_min, int p, uint32_t& ca, uint32_t& n)
+{
+    // p's segment: it starts at the valid sample x and holds cnt valid
+    // samples (the record sits in the slot of x)
+    const int sidp = segid[cd.off + p];
+    int x = -1, cnt = 0;
+    if (sidp <= -2) {
+        x = p;
+        cnt = -2 - sidp;
+    } else if (sidp >= 0 && sidp < p) {
+        const int rec = segid[cd.off + sidp];
+        x = sidp;
+        cnt = rec <= -2 ? -2 - rec : 0;
+    }
+    if (x < 0 || cnt < m_min) return false;
+    int a = max(p - h, x);
+    // the window ends before the next segment's first sample: the first
+    // start bit after p within reach of p + h
+    const uint32_t from = (uint32_t)(p + 1 - s0);
+    uint32_t lim = (uint32_t)(min(p + h, s0 + N - 1) - s0);
+    uint32_t wi = from >> 6;
+    uint64_t sb = sm.sbits[wi] & (~0ull << (from & 63u));
+    while (sb == 0ull && (wi << 6) + 64u <= lim) sb = sm.sbits[++wi];
+    if (sb != 0ull) {
+        const uint32_t nx = (wi << 6) + (uint32_t)__builtin_ctzll(sb);
+        if (nx <= lim) lim = nx - 1u;
+    }
+    int b = s0 + (int)lim;
+    if (cd.window_days > 0.0) {
+        // time window: only the samples within half its length of p count.
+        // Times are non-decreasing, so they form a run that two scans in from
+        // the index window's ends find (invalid samples inside it are skipped
+        // by the ranks).
+        const double* tc = time + cd.off;
+        const double ti = tc[p];
+        const double half = 0.5 * cd.window_days;
+        while (a < p && !(__builtin_fabs(tc[a] - ti) <= half)) ++a;
+        while (b > p && !(__builtin_fabs(tc[b] - ti) <= half)) --b;
+    }
+    ca = rank1(sm.vbits, sm.vpre, (uint32_t)(a - s0));
+    n = rank1(sm.vbits, sm.vpre, (uint32_t)(b - s0 + 1)) - ca;  // >= 1: p is valid
+    return true;
+}
+
+// Phase 1 of the window at compacted [ca, ca + n) from the sorted tile and
+// the wavelet matrix: the median m, and either n+ (the points strictly
+// above m, for Eq. 1) or, with the MAD ablation, the scale itself.
+__device__ __forceinline__ void window_phase1(const MainSmem& sm, int levels, int nv, int scale,
+                                              uint32_t ca, uint32_t n, float& m, float& sc,
+                                              uint32_t& nplus)
+{
+    const uint32_t cb = ca + n;
+    const uint32_t rk = wavelet_kth(sm, levels, ca, cb, (n - 1) >> 1);
+    m = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
+    if (scale == UMI_SCALE_MAD) {
+        sc = window_mad(sm, levels, ca, n, m);
+        return;
+    }
+    // the points strictly above m are the window's elements ranked after
+    // the last tile element numerically equal to m (ties and -0/+0 sit next
+    // to m in the sorted order); a galloping search: one probe without ties,
+    // O(log) with many
+    uint32_t rh = rk, hi = rk + 1, step = 1;
+    while (hi < (uint32_t)nv && key_value((uint32_t)(sm.sortbuf[hi] >> 32)) == m) {
+        rh = hi;
+        hi = rh + (step <<= 1);
+    }
+    if (hi > (uint32_t)nv) hi = (uint32_t)nv;
+    while (hi - rh > 1u) {  // last equal in [rh, hi)
+        const uint32_t mid = (rh + hi) >> 1;
+        if (key_value((uint32_t)(sm.sortbuf[mid] >> 32)) == m)
+            rh = mid;
+        else
+            hi = mid;
+    }
+    // exactly k + 1 window elements rank at or below rk (rk is the window's
+    // k-th); of the tile elements tied with m after rk, count those in the
+    // window directly when they are few, else with a wavelet descent
+    const uint32_t k = (n - 1) >> 1;
+    if (rh - rk <= 16u) {
+        uint32_t tied = 0;
+        for (uint32_t j = rk + 1; j <= rh; ++j)
+            tied += ((uint32_t)(sm.sortbuf[j] & 0xffffffffull) - ca < n) ? 1u : 0u;
+        nplus = n - k - 1 - tied;
+    } else {
+        nplus = n - wavelet_count_less(sm, levels, ca, cb, rh + 1);
+    }
+}
+
 // The windows of one tile: each lane takes R consecutive output positions.
 template <int R>
 __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int nv,
-                                             const CurveDesc& cd, int h, int s0, int t0, int t1,
-                                             const int32_t* __restrict__ segid,
-                                             const int4* __restrict__ segtab, float alpha,
+                                             const CurveDesc& cd, int h, int s0, int N, int t0,
+                                             int t1,
+                                             const int32_t* __restrict__ segid, float alpha,
                                              float c, int iters, int scale, bool simple,
                                              const float* pm, const uint32_t* pn,
                                              const double* __restrict__ time,
@@ -633,33 +762,9 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int p = pfirst + r;
-        live[r] = false;
         ca[r] = 0;
         n[r] = 0;
-        if (p < t1) {
-            const int sidp = segid[cd.off + p];
-            if (sidp >= 0) {
-                const int4 seg = segtab[cd.off + sidp];
-                if (seg.w - seg.z >= m_min) {
-                    int a = max(p - h, seg.x);
-                    int b = min(p + h, seg.y);
-                    if (cd.window_days > 0.0) {
-                        // time window: only the samples within half its length
-                        // of p count.  Times are non-decreasing, so they form a
-                        // run that two scans in from the index window's ends find
-                        // (invalid samples inside it are skipped by the ranks).
-                        const double* tc = time + cd.off;
-                        const double ti = tc[p];
-                        const double half = 0.5 * cd.window_days;
-                        while (a < p && !(__builtin_fabs(tc[a] - ti) <= half)) ++a;
-                        while (b > p && !(__builtin_fabs(tc[b] - ti) <= half)) --b;
-                    }
-                    ca[r] = rank1(sm.vbits, sm.vpre, (uint32_t)(a - s0));
-                    n[r] = rank1(sm.vbits, sm.vpre, (uint32_t)(b - s0 + 1)) - ca[r];  // >= 1: p is valid
-                    live[r] = true;
-                }
-            }
-        }
+        live[r] = p < t1 && window_range(sm, cd, segid, time, h, s0, N, m_min, p, ca[r], n[r]);
     }
     // The common case -- every window of the wave live, of one length, and
     // consecutive -- runs the fused loops with a wave-uniform trip count.
@@ -681,21 +786,7 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
             m[r] = pm[r];  // from the small-window networks
             nplus[r] = pn[r];
         } else if (live[r]) {
-            const uint32_t cb = ca[r] + n[r];
-            const uint32_t rk = wavelet_kth(sm, levels, ca[r], cb, (n[r] - 1) >> 1);
-            m[r] = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
-            if (scale == UMI_SCALE_MAD) {
-                sc[r] = window_mad(sm, levels, ca[r], n[r], m[r]);
-            } else {
-                // the points strictly above m are the window's elements ranked
-                // after the last tile element numerically equal to m (ties and
-                // -0/+0 sit next to m in the sorted order)
-                uint32_t rh = rk;
-                while (rh + 1 < (uint32_t)nv &&
-                       key_value((uint32_t)(sm.sortbuf[rh + 1] >> 32)) == m[r])
-                    ++rh;
-                nplus[r] = n[r] - wavelet_count_less(sm, levels, ca[r], cb, rh + 1);
-            }
+            window_phase1(sm, levels, nv, scale, ca[r], n[r], m[r], sc[r], nplus[r]);
         }
     }
     if (scale != UMI_SCALE_MAD) {
@@ -754,9 +845,103 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split windows: G lanes share one window (tiles of at most kMainThreads / G
+// output positions).  Lane l of a group sums the window samples l, l + G,
+// l + 2G, ... in order, and a butterfly over the group's G consecutive lanes
+// combines the partial sums -- lane xor 1 and xor 2 by DPP quad permutes,
+// xor 4 by a ds_swizzle -- in one fixed order.  Every lane of a group ends
+// with the same bits (IEEE addition commutes), so the group's lanes iterate
+// in step.  The sums are ordered differently from the one-lane-per-window
+// path, so the two agree to rounding, not bit for bit; each is deterministic.
+
+__device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float dpp_xor2(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float swizzle_xor4(float v)
+{
+    // bitmask mode: and 0x1f, or 0, xor 4 (lanes within 32-lane halves)
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+    static_assert(G == 2 || G == 4 || G == 8, "group of 2, 4 or 8 lanes");
+    v = v + dpp_xor1(v);
+    if (G >= 4) v = v + dpp_xor2(v);
+    if (G >= 8) v = v + swizzle_xor4(v);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int levels, int nv,
+                                                   const CurveDesc& cd, int h, int s0, int N,
+                                                   int t0, int t1,
+                                                   const int32_t* __restrict__ segid,
+                                                   float alpha, float c, int iters, int scale,
+                                                   const double* __restrict__ time,
+                                                   float* __restrict__ trend,
+                                                   float* __restrict__ median,
+                                                   float* __restrict__ detrended)
+{
+    const int m_min = max(1, cd.W / 3);
+    const int l = (int)threadIdx.x & (G - 1);
+    const int p = t0 + (int)threadIdx.x / G;
+    uint32_t ca = 0, n = 0;
+    const bool live = p < t1 && window_range(sm, cd, segid, time, h, s0, N, m_min, p, ca, n);
+    float m = 0.0f, sc = 0.0f;
+    uint32_t nplus = 0;
+    if (live) window_phase1(sm, levels, nv, scale, ca, n, m, sc, nplus);  // same on every lane
+    const float* x = sm.xv + ca;
+    if (live && scale != UMI_SCALE_MAD) {
+        // Phase 2 (Eq. 1)
+        float ssq = 0.0f;
+        for (int j = l; j < (int)n; j += G) {
+            const float d = __builtin_fmaxf(x[j] - m, 0.0f);
+            ssq = __builtin_fmaf(d, d, ssq);
+        }
+        ssq = group_sum<G>(ssq);
+        if (nplus > 0) sc = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
+    }
+    // Phase 3 (Eqs. 2-4), as in the one-lane path
+    float mu = m;
+    const float kA = 0.5f * (1.0f + alpha);
+    const float beta = (1.0f - alpha) / (1.0f + alpha);
+    const float kk = live && sc > 0.0f ? kA / (c * sc) : 0.0f;
+    if (live && sc > 0.0f && iters > 0 && isfinite(kk)) {
+        for (int it = 0; it < iters; ++it) {
+            const float b = -mu * kk;
+            float sw = 0.0f, swv = 0.0f;
+            for (int j = l; j < (int)n; j += G) bisquare_acc(x[j], kk, b, beta, sw, swv);
+            sw = group_sum<G>(sw);
+            swv = group_sum<G>(swv);
+            if (!(sw > 0.0f)) break;  // no weight left: keep mu
+            mu = mu + swv / (sw * kk);
+        }
+    }
+    if (p < t1 && l == 0) {
+        const float nanf_ = __builtin_nanf("");
+        trend[cd.off + p] = live ? mu : nanf_;
+        if (median) median[cd.off + p] = live ? m : nanf_;
+        if (detrended) {
+            float d = nanf_;
+            if (live) d = sm.xv[rank1(sm.vbits, sm.vpre, (uint32_t)(p - s0))] / mu;
+            detrended[cd.off + p] = d;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const float* __restrict__ flux, const int32_t* __restrict__ segid,
-    const int4* __restrict__ segtab, const BatchHeader* __restrict__ hdr,
+    const BatchHeader* __restrict__ hdr,
     const CurveDesc* __restrict__ curves, const int2* __restrict__ tiles, int tile_first,
     int tile_count, uint32_t* __restrict__ counter, float* __restrict__ trend,
     float* __restrict__ median)
@@ -797,20 +982,29 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         // A tile is "simple" when every one of its windows is full: a small
         // W, no curve end within reach, and the whole span valid and in one
         // segment.  Its medians then come from per-window networks.
+        // segment of staged sample i (the start index of its segment, -1 if
+        // invalid): a segment's first slot holds its record instead
         const int sg0 = sg[0];
+        const int seg0 = sg0 >= 0 ? sg0 : (sg0 == -1 ? -1 : s0);
         bool same = true;
         const int nwv = (N >> 6) + 1;
         for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
             const int i = i0 + lane;
             const int sgi = i < N ? sg[i] : sg0;
-            const bool ok = (i < N) && (sgi >= 0);
-            same = same && sgi == sg0;
+            const bool ok = (i < N) && (sgi != -1);
+            const int segi = i < N ? (sgi >= 0 ? sgi : (sgi == -1 ? -1 : s0 + i)) : seg0;
+            same = same && segi == seg0;
             const uint64_t bal = __ballot(ok);
-            if (lane == 0) sm.vbits[i0 >> 6] = bal;
+            const uint64_t st = __ballot(ok && sgi <= -2);
+            if (lane == 0) {
+                sm.vbits[i0 >> 6] = bal;
+                sm.sbits[i0 >> 6] = st;
+            }
         }
-        const bool simple = __syncthreads_and(same) && sg0 >= 0 && cd.W <= kSmallW &&
+        const int G = split_lanes(cd.tile);  // lanes per window (1: R windows per lane)
+        const bool simple = __syncthreads_and(same) && seg0 >= 0 && cd.W <= kSmallW &&
                             scale != UMI_SCALE_MAD && cd.window_days == 0.0 && t0 >= h &&
-                            t1 + h <= cd.len;
+                            t1 + h <= cd.len && G == 1;
         word_prefix(sm.vbits, sm.vpre, nwv, reinterpret_cast<uint32_t*>(&sm.nvalid));
         __syncthreads();
         const int nv = sm.nvalid;
@@ -832,7 +1026,7 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         // --- compaction: values in index order, (key, index) for the sort ---
         for (int i0 = wave * 64; i0 < nwv * 64; i0 += kMainThreads) {
             const int i = i0 + lane;
-            if (i < N && sg[i] >= 0) {
+            if (i < N && sg[i] != -1) {
                 const float x = f[i];
                 const uint32_t ci = rank1(sm.vbits, sm.vpre, (uint32_t)i);
                 sm.xv[ci] = x;
@@ -898,7 +1092,21 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         }
         }  // not simple
 
-        // --- the tile's windows: R consecutive positions per lane ---
+        // --- the tile's windows: G lanes per position, or R consecutive
+        // positions per lane ---
+        if (G > 1) {
+            if (G == 2)
+                tile_windows_split<2>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                                      scale, time, trend, median, detrended);
+            else if (G == 4)
+                tile_windows_split<4>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                                      scale, time, trend, median, detrended);
+            else
+                tile_windows_split<8>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                                      scale, time, trend, median, detrended);
+            __syncthreads();
+            continue;
+        }
         const int R = (t1 - t0 + kMainThreads - 1) / kMainThreads;  // tile <= kMaxTile -> R <= 3
         // Simple tiles: Phase 1 of this lane's windows from the networks, run
         // here where few registers are live (every window is [p-h, p+h], all
@@ -917,13 +1125,13 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
         }
         if (R == 3)
-            tile_windows<3>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+            tile_windows<3>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         else if (R == 2)
-            tile_windows<2>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+            tile_windows<2>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         else
-            tile_windows<1>(sm, levels, nv, cd, h, s0, t0, t1, segid, segtab, alpha, c, iters, scale,
+            tile_windows<1>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         __syncthreads();
     }
@@ -934,32 +1142,31 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
                           const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
-                          int4* segtab, int2* tiles, uint32_t* counter, hipStream_t stream)
+                          int2* tiles, uint32_t* counter, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
     // A launch over few curves walks each curve with a 1024-thread workgroup
-    // (a quarter as many chunks in sequence); many curves fill the chip with
-    // 256-thread workgroups, one per curve.
+    // of 8 samples per thread (an eighth as many chunks in sequence); many
+    // curves fill the chip with 256-thread workgroups, one per curve.
     if (grid <= kPrepWideCurves)
-        hipLaunchKernelGGL(umi_prepass_kernel<kPrepWideThreads>, dim3(grid),
+        hipLaunchKernelGGL((umi_prepass_kernel<kPrepWideThreads, kPrepWideItems>), dim3(grid),
                            dim3(kPrepWideThreads), 0, stream, flux, time, hdr, curves,
-                           curve_first, segid, segtab, tiles, counter);
+                           curve_first, segid, tiles, counter);
     else
-        hipLaunchKernelGGL(umi_prepass_kernel<kPrepThreads>, dim3(grid), dim3(kPrepThreads), 0,
-                           stream, flux, time, hdr, curves, curve_first, segid, segtab, tiles,
-                           counter);
+        hipLaunchKernelGGL((umi_prepass_kernel<kPrepThreads, kPrepItems>), dim3(grid),
+                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves, curve_first,
+                           segid, tiles, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_main(const float* flux, const int32_t* segid, const int4* segtab,
-                       const BatchHeader* hdr, const CurveDesc* curves, const int2* tiles,
-                       int tile_first, int tile_count, uint32_t* counter, int grid,
-                       float* trend, float* median, hipStream_t stream)
+hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
+                       const CurveDesc* curves, const int2* tiles, int tile_first,
+                       int tile_count, uint32_t* counter, int grid, float* trend, float* median,
+                       hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(umi_main_kernel, dim3(grid), dim3(kMainThreads), 0, stream, flux, segid,
-                       segtab, hdr, curves, tiles, tile_first, tile_count, counter, trend,
-                       median);
+                       hdr, curves, tiles, tile_first, tile_count, counter, trend, median);
     return hipGetLastError();
 }
 

@@ -41,8 +41,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # Device bytes held per resident sample: flux f32, time f64, trend f32, and
-# the plan workspace (segment id i32 + segment record 4 x i32).
-BYTES_PER_SAMPLE = 4 + 8 + 4 + 4 + 16
+# the plan workspace: one i32 segment word per sample plus the tile list
+# (8 bytes per tile of at least 512 samples, rounded up to 1 byte per sample).
+BYTES_PER_SAMPLE = 4 + 8 + 4 + 4 + 1
 
 
 class Rejected(ValueError):
@@ -531,8 +532,14 @@ class Server:
                 raise ValueError("flux and time must be 1-D of equal length")
             if W < 1 or W % 2 == 0 or W > self.max_W:
                 raise ValueError("W must be odd, 1 <= W <= %d" % self.max_W)
-            if not (alpha > 0 and c > 0 and iters >= 0):
-                raise ValueError("need alpha > 0, c > 0, iters >= 0")
+            # the kernels take alpha and c as float32: a value that overflows
+            # or flushes there would fail the whole step it shares
+            with np.errstate(over="ignore"):
+                a32, c32 = np.float32(alpha), np.float32(c)
+            if not (np.isfinite(a32) and a32 > 0 and np.isfinite(c32) and c32 > 0):
+                raise ValueError("alpha and c must be finite and > 0 as float32")
+            if int(iters) != iters or iters < 0:
+                raise ValueError("iters must be an integer >= 0")
             if flux.size > self.arena.capacity:
                 raise Rejected("curve of %d samples exceeds the device budget of %d samples"
                                % (flux.size, self.arena.capacity))

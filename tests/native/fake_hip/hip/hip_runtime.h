@@ -1,0 +1,130 @@
+// Host-only stand-in for the subset of the HIP runtime API that the library's
+// host code (umi_host.hip) calls, so that code can be built with g++ and run
+// under the address, undefined-behaviour and thread sanitizers on a machine
+// without a GPU.  "Device" memory is host memory, copies are memcpy, streams,
+// events and graphs do nothing, and one device with 256 compute units exists.
+// Kernel launches are not part of it: the test driver supplies the launch
+// wrappers the host code calls.  Test infrastructure only.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+
+#define __host__
+#define __device__
+#define __global__
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) (&(x))
+
+struct int2 { int x, y; };
+struct int4 { int x, y, z, w; };
+inline int2 make_int2(int x, int y) { return int2{x, y}; }
+
+typedef enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1,
+               hipErrorNoDevice = 100 } hipError_t;
+typedef enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 } hipMemcpyKind;
+typedef enum { hipDeviceAttributeMultiprocessorCount = 16 } hipDeviceAttribute_t;
+typedef enum { hipStreamCaptureModeThreadLocal = 1 } hipStreamCaptureMode;
+typedef struct ihipStream_t* hipStream_t;
+typedef struct ihipEvent_t* hipEvent_t;
+typedef struct ihipGraph_t* hipGraph_t;
+typedef struct ihipGraphExec_t* hipGraphExec_t;
+typedef struct ihipGraphNode_t* hipGraphNode_t;
+#define hipEventDisableTiming 2u
+#define hipHostMallocDefault 0u
+
+namespace fake_hip {
+// counters the driver reads to check that calls balance
+inline long& live_device_blocks() { static long n = 0; return n; }
+inline long& live_host_blocks() { static long n = 0; return n; }
+inline long& live_events() { static long n = 0; return n; }
+inline long& live_graphs() { static long n = 0; return n; }
+inline long& device_mallocs() { static long n = 0; return n; }
+}  // namespace fake_hip
+
+inline const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "fake hip error"; }
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipSetDevice(int) { return hipSuccess; }
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
+inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
+inline hipError_t hipMalloc(void** p, size_t n)
+{
+    *p = std::malloc(n ? n : 1);
+    if (!*p) return hipErrorOutOfMemory;
+    ++fake_hip::live_device_blocks();
+    ++fake_hip::device_mallocs();
+    return hipSuccess;
+}
+inline hipError_t hipFree(void* p)
+{
+    if (p) --fake_hip::live_device_blocks();
+    std::free(p);
+    return hipSuccess;
+}
+inline hipError_t hipHostMalloc(void** p, size_t n, unsigned)
+{
+    *p = std::malloc(n ? n : 1);
+    if (!*p) return hipErrorOutOfMemory;
+    ++fake_hip::live_host_blocks();
+    return hipSuccess;
+}
+inline hipError_t hipHostFree(void* p)
+{
+    if (p) --fake_hip::live_host_blocks();
+    std::free(p);
+    return hipSuccess;
+}
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t)
+{
+    if (n) std::memcpy(d, s, n);
+    return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned)
+{
+    *e = reinterpret_cast<hipEvent_t>(new char[1]);
+    ++fake_hip::live_events();
+    return hipSuccess;
+}
+inline hipError_t hipEventDestroy(hipEvent_t e)
+{
+    if (e) --fake_hip::live_events();
+    delete[] reinterpret_cast<char*>(e);
+    return hipSuccess;
+}
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g)
+{
+    *g = reinterpret_cast<hipGraph_t>(new char[1]);
+    ++fake_hip::live_graphs();
+    return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t, hipGraphNode_t*, char*, size_t)
+{
+    *x = reinterpret_cast<hipGraphExec_t>(new char[1]);
+    ++fake_hip::live_graphs();
+    return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t x)
+{
+    if (x) --fake_hip::live_graphs();
+    delete[] reinterpret_cast<char*>(x);
+    return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g)
+{
+    if (g) --fake_hip::live_graphs();
+    delete[] reinterpret_cast<char*>(g);
+    return hipSuccess;
+}
+template <class T>
+inline hipError_t hipGetSymbolAddress(void** p, T sym)
+{
+    *p = const_cast<void*>(static_cast<const void*>(sym));
+    return hipSuccess;
+}

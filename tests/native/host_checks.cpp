@@ -1,0 +1,293 @@
+// Sanitizer driver for the library's host code (test infrastructure).
+//
+// Built with g++ against the host-only HIP stand-in (tests/native/fake_hip),
+// together with the host source itself, and run under AddressSanitizer +
+// UndefinedBehaviorSanitizer or ThreadSanitizer.  The kernel launch wrappers
+// are replaced by checkers that read what the host staged for the kernels
+// (batch header, curve table) and touch every sample, segment word and tile
+// slot a launch may touch, so a packer or workspace that under-sizes
+// anything, or an offset outside the caller's arrays, is an out-of-bounds
+// access the sanitizer reports.  Exercised: argument checks, the tuning
+// table, direct batches (packed and gathered, with options and explicit
+// launches), plans (create / run / destroy, both graph kinds), the
+// allocation-free batch call, the host copy pool from several threads at
+// once, and umi_release.  Prints "host checks ok" and exits 0 on success.
+// An optional argument sets the number of random batches per pass.
+#include "umi_host.hip"
+
+#include <random>
+#include <thread>
+
+namespace {
+
+int g_failures = 0;
+long g_prepass = 0, g_main = 0;
+
+#define CHECK(cond)                                                               \
+    do {                                                                          \
+        if (!(cond)) {                                                            \
+            std::fprintf(stderr, "CHECK failed at line %d: %s\n", __LINE__, #cond); \
+            ++g_failures;                                                         \
+        }                                                                         \
+    } while (0)
+
+}  // namespace
+
+namespace umi {
+
+// The pre-pass: every curve of the grid reads its flux and time and writes
+// a segment word per sample and its tile records (what the kernel writes).
+hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
+                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
+                          int2* tiles, uint32_t* counter, hipStream_t)
+{
+    ++g_prepass;
+    if (counter) *counter = 0u;
+    CHECK(hdr->n_curves >= 0 && hdr->n_tiles >= 0);
+    for (int b = 0; b < grid; ++b) {
+        const int ci = curve_first + b;
+        if (ci >= hdr->n_curves) break;
+        const CurveDesc& cd = curves[ci];
+        CHECK(cd.len > 0 && cd.W >= 1 && (cd.W & 1) == 1 && cd.tile >= 1);
+        CHECK(cd.tile <= kMaxTile && cd.tile + cd.W - 1 <= kStageMax);
+        const int nt = (cd.len + cd.tile - 1) / cd.tile;
+        CHECK(cd.tile_base >= 0 && cd.tile_base + nt <= hdr->n_tiles);
+        for (int t = 0; t < nt; ++t) tiles[cd.tile_base + t] = make_int2(ci, t * cd.tile);
+        volatile float fs = 0.0f;
+        volatile double ts = 0.0;
+        for (int i = 0; i < cd.len; ++i) {
+            fs = fs + flux[cd.off + i];
+            if (time) ts = ts + time[cd.off + i];
+            segid[cd.off + i] = -1;
+        }
+        if (hdr->detrended)
+            for (int i = 0; i < cd.len; ++i) hdr->detrended[cd.off + i] = 0.0f;
+        if (hdr->time) CHECK(hdr->time == time);
+    }
+    return hipSuccess;
+}
+
+// The estimate kernel: every tile of its range lies in its curve, its
+// staged span fits the workgroup, and the outputs of its positions exist.
+hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
+                       const CurveDesc* curves, const int2* tiles, int tile_first,
+                       int tile_count, uint32_t* counter, int grid, float* trend, float* median,
+                       hipStream_t)
+{
+    ++g_main;
+    CHECK(grid >= 1);
+    const int end = tile_count < 0 ? hdr->n_tiles : tile_first + tile_count;
+    CHECK(end <= hdr->n_tiles);
+    if (counter) CHECK(*counter == 0u);
+    for (int t = tile_first; t < end; ++t) {
+        const int2 td = tiles[t];
+        CHECK(td.x >= 0 && td.x < hdr->n_curves);
+        const CurveDesc& cd = curves[td.x];
+        const int h = (cd.W - 1) / 2;
+        const int t0 = td.y, t1 = std::min(t0 + cd.tile, cd.len);
+        CHECK(t0 >= 0 && t0 < cd.len && t0 % cd.tile == 0);
+        const int s0 = std::max(t0 - h, 0), s1 = std::min(t1 + h, cd.len);
+        CHECK(s1 - s0 <= kStageMax);
+        CHECK(split_lanes(cd.tile) * std::min(cd.tile, kMainThreads) <= kMainThreads ||
+              split_lanes(cd.tile) == 1);
+        volatile float fs = 0.0f;
+        for (int i = s0; i < s1; ++i) fs = fs + flux[cd.off + i] + (float)segid[cd.off + i];
+        for (int p = t0; p < t1; ++p) {
+            trend[cd.off + p] = 1.0f;
+            if (median) median[cd.off + p] = 1.0f;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace umi
+
+namespace {
+
+std::mt19937_64 rng(2604066020ull);
+
+int64_t uni(int64_t lo, int64_t hi) { return std::uniform_int_distribution<int64_t>(lo, hi)(rng); }
+
+struct DevArrays {
+    float* flux = nullptr;
+    double* time = nullptr;
+    float* trend = nullptr;
+    float* median = nullptr;
+    float* det = nullptr;
+    explicit DevArrays(int64_t n)
+    {
+        void* p;
+        hipMalloc(&p, sizeof(float) * (size_t)n); flux = (float*)p;
+        hipMalloc(&p, sizeof(double) * (size_t)n); time = (double*)p;
+        hipMalloc(&p, sizeof(float) * (size_t)n); trend = (float*)p;
+        hipMalloc(&p, sizeof(float) * (size_t)n); median = (float*)p;
+        hipMalloc(&p, sizeof(float) * (size_t)n); det = (float*)p;
+        for (int64_t i = 0; i < n; ++i) {
+            flux[i] = 1.0f;
+            time[i] = (double)i / 720.0;
+        }
+    }
+    ~DevArrays()
+    {
+        hipFree(flux); hipFree(time); hipFree(trend); hipFree(median); hipFree(det);
+    }
+};
+
+int32_t odd_w(int64_t max_w) { return (int32_t)(uni(0, (max_w - 1) / 2) * 2 + 1); }
+
+void check_tuning()
+{
+    CHECK(umi_set_tuning("31 2000 4\n127 1500 3\n2047 0 0\n") == UMI_OK);
+    CHECK(umi_set_tuning("31 64 4 40000\n31 512 4 160000\n31 1536 4\n2047 128 4 9000\n2047 0 4\n") == UMI_OK);
+    CHECK(umi_set_tuning("31 10 2\n31 10 2 50") == UMI_ERR_INVALID_ARG);
+    CHECK(umi_set_tuning("127 1 2\n31 1 2") == UMI_ERR_INVALID_ARG);
+    CHECK(umi_set_tuning("x") == UMI_ERR_INVALID_ARG);
+}
+
+int g_rounds = 300;  // batches per pass (the thread-sanitizer run takes fewer)
+
+void check_direct_batches()
+{
+    for (int round = 0; round < g_rounds; ++round) {
+        const int64_t n = uni(0, 40);
+        std::vector<int64_t> len((size_t)n), off((size_t)n);
+        std::vector<int32_t> W((size_t)n);
+        std::vector<float> al((size_t)n), cc((size_t)n);
+        std::vector<double> wd((size_t)n);
+        int64_t total = 0;
+        for (int64_t b = 0; b < n; ++b) {
+            const int kind = (int)uni(0, 9);
+            len[b] = kind == 0 ? 0 : (kind == 1 ? uni(1, 5) : uni(1, 60000));
+            W[b] = odd_w(uni(0, 3) == 0 ? UMI_MAX_WINDOW : 721);
+            al[b] = (float)uni(1, 10);
+            cc[b] = (float)uni(1, 5);
+            wd[b] = uni(0, 3) == 0 ? 0.5 : 0.0;
+            total += len[b];
+        }
+        const bool gather = uni(0, 1) == 1;
+        int64_t span = 0;
+        for (int64_t b = 0; b < n; ++b) {  // packed, or gathered with gaps in between
+            off[b] = span + (gather ? uni(0, 1000) : 0);
+            span = off[b] + len[b];
+        }
+        DevArrays a(std::max<int64_t>(span, 1));
+        umi_launch lo = {UMI_MODE_PERSISTENT, 0, 0, 0, nullptr, nullptr};
+        const int lk = (int)uni(0, 5);
+        if (lk == 1) lo.tile = (int32_t)uni(1, 3000);
+        if (lk == 2) lo.mode = UMI_MODE_PER_CURVE;
+        if (lk == 3) lo.groups_per_cu = (int32_t)uni(1, 8);
+        if (lk == 4) lo.tile = (int32_t)(uni(0, 1) ? 64 : 256);
+        umi_options o = {uni(0, 1) ? al.data() : nullptr, uni(0, 1) ? cc.data() : nullptr,
+                         (int32_t)uni(0, 1), 0, uni(0, 1) ? a.det : nullptr,
+                         uni(0, 1) ? wd.data() : nullptr};
+        umi_status st;
+        if (gather)
+            st = umi_detrend_gather_ex(a.flux, a.time, off.data(), len.data(), n, W.data(), 2.0f,
+                                       5.0f, 5, a.trend, uni(0, 1) ? a.median : nullptr, &o, &lo,
+                                       nullptr);
+        else
+            st = umi_detrend_batch(a.flux, uni(0, 3) ? a.time : nullptr, len.data(), n, W.data(),
+                                   2.0f, 5.0f, 5, a.trend, a.median, &lo, nullptr);
+        CHECK(st == UMI_OK);
+        if (st != UMI_OK) std::fprintf(stderr, "  %s\n", umi_last_error());
+        // invalid arguments are refused before anything is enqueued
+        if (n > 0) {
+            std::vector<int32_t> Wbad = W;
+            Wbad[0] = 4;
+            const long before = g_prepass;
+            CHECK(umi_detrend_batch(a.flux, a.time, len.data(), n, Wbad.data(), 2.0f, 5.0f, 5,
+                                    a.trend, nullptr, nullptr, nullptr) == UMI_ERR_INVALID_ARG);
+            CHECK(g_prepass == before);
+        }
+        (void)total;
+    }
+}
+
+void check_plans()
+{
+    for (int round = 0; round < std::max(2, g_rounds / 15); ++round) {
+        const int64_t cap = uni(1000, 400000);
+        const int64_t max_curves = uni(1, 100);
+        const int32_t max_w = odd_w(721);
+        DevArrays a(cap);
+        umi_plan* p = nullptr;
+        CHECK(umi_plan_create(&p, cap, max_curves, max_w, a.flux, a.time, a.trend, a.median,
+                              reinterpret_cast<void*>(uintptr_t(0x1000))) == UMI_OK);
+        if (!p) continue;
+        for (int run = 0; run < 30; ++run) {
+            const int64_t n = uni(0, max_curves);
+            std::vector<int64_t> len((size_t)n), off((size_t)n);
+            std::vector<int32_t> W((size_t)n);
+            int64_t pos = 0;
+            bool fits = true;
+            for (int64_t b = 0; b < n; ++b) {
+                len[b] = uni(0, std::max<int64_t>(1, cap / std::max<int64_t>(n, 1)));
+                off[b] = pos + uni(0, 3);
+                pos = off[b] + len[b];
+                W[b] = odd_w(max_w);
+            }
+            if (pos > cap) fits = false;
+            const umi_status st = umi_plan_run(p, off.data(), len.data(), W.data(), n, 2.0f, 5.0f, 5);
+            if (fits) {
+                CHECK(st == UMI_OK);
+                if (st != UMI_OK) std::fprintf(stderr, "  plan: %s\n", umi_last_error());
+            } else {
+                CHECK(st == UMI_ERR_INVALID_ARG);
+            }
+        }
+        CHECK(umi_plan_destroy(p) == UMI_OK);
+    }
+}
+
+void check_copy_pool()
+{
+    auto worker = [](int seed) {
+        std::mt19937_64 r((uint64_t)seed);
+        for (int it = 0; it < 20; ++it) {
+            const int n = (int)(r() % 12);
+            std::vector<std::vector<char>> src((size_t)n), dst((size_t)n);
+            std::vector<void*> d((size_t)n);
+            std::vector<const void*> s((size_t)n);
+            std::vector<int64_t> bytes((size_t)n);
+            for (int i = 0; i < n; ++i) {
+                bytes[i] = (int64_t)(r() % (3u << 20));
+                src[i].assign((size_t)bytes[i], (char)(i + seed));
+                dst[i].assign((size_t)bytes[i], 0);
+                d[i] = dst[i].data();
+                s[i] = src[i].data();
+            }
+            const int threads = 1 + (int)(r() % 8);
+            CHECK(umi_host_copy_many(d.data(), s.data(), bytes.data(), n, threads) == UMI_OK);
+            for (int i = 0; i < n; ++i) CHECK(dst[i] == src[i]);
+        }
+    };
+    std::vector<std::thread> ts;
+    for (int k = 0; k < 4; ++k) ts.emplace_back(worker, k + 1);
+    for (auto& t : ts) t.join();
+}
+
+}  // namespace
+
+int main(int argc, char** argv)
+{
+    if (argc > 1) g_rounds = std::max(1, std::atoi(argv[1]));
+    check_tuning();
+    check_direct_batches();
+    CHECK(umi_set_tuning(nullptr) == UMI_OK);
+    check_direct_batches();
+    check_plans();
+    check_copy_pool();
+    umi_release();
+    CHECK(fake_hip::live_device_blocks() == 0);
+    CHECK(fake_hip::live_host_blocks() == 0);
+    CHECK(fake_hip::live_events() == 0);
+    CHECK(fake_hip::live_graphs() == 0);
+    CHECK(g_prepass > 0 && g_main > 0);
+    if (g_failures) {
+        std::fprintf(stderr, "%d host checks failed\n", g_failures);
+        return 1;
+    }
+    std::printf("host checks ok (%ld pre-pass and %ld estimate launches checked)\n", g_prepass,
+                g_main);
+    return 0;
+}

@@ -114,8 +114,12 @@ def test_injected_error_propagates_once(lib):
 
 def test_tuning_table_parsing(lib):
     lib.set_tuning("# W_max tile groups\n31 2000 4\n127 1500 3\n\n2047 0 0\n")
+    # batch-size rows precede a bucket's row for any size, smallest first
+    lib.set_tuning("31 64 4 40000\n31 512 4 160000\n31 1536 4\n127 128 4 40000\n127 1536 4 0\n")
     lib.set_tuning(None)
-    for bad in ["31 2000", "31 2000 4 9", "127 10 2\n31 10 2", "x 1 2", "31 -1 2", "31 10 99"]:
+    for bad in ["31 2000", "31 2000 4 9 1", "127 10 2\n31 10 2", "x 1 2", "31 -1 2", "31 10 99",
+                "31 10 2 -5", "31 10 2 x", "31 10 2\n31 10 2 50", "31 10 2 50\n31 10 2 50",
+                "31 10 2 50\n31 10 2 40"]:
         with pytest.raises(lib.UmiError):
             lib.set_tuning(bad)
     lib.set_tuning(None)
@@ -202,9 +206,12 @@ def test_autotune_table_is_loadable(lib, monkeypatch):
     assert table is not None, "no committed tuning table for this library version"
     lib.set_tuning(table)          # the library accepts it
     lib.set_tuning(None)
-    rows = [tuple(map(int, l.split())) for l in table.strip().splitlines()]
-    assert [r[0] for r in rows] == [b[0] for b in autotune.BUCKETS]
-    for w_max, tile, gpc in rows:
+    rows = [(tuple(map(int, l.split())) + (0,))[:4] for l in table.strip().splitlines()]
+    general = [r for r in rows if r[3] == 0]
+    assert [r[0] for r in general] == [b[0] for b in autotune.BUCKETS]
+    sized = {(r[0], r[3]) for r in rows if r[3] > 0}
+    assert sized == {(b[0], s) for b in autotune.BUCKETS for _, s in autotune.SMALL_BATCHES}
+    for w_max, tile, gpc, _ in rows:
         assert 1 <= tile <= autotune.max_tile(dict(autotune.BUCKETS)[w_max])
         assert 1 <= gpc <= 4
 

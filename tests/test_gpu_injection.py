@@ -6,9 +6,14 @@ paper states, never stored numbers:
   * far below the per-cadence noise (5 ppm) every setting is noise-limited;
   * well above it the asymmetric default beats the symmetric reference, and
     the aggressive setting (alpha 10, c 2.5) recovers deep transits best.
+
+The second half runs the HIP path and the FP64 oracle on the same seeded
+inputs: the white-noise bias check (Sections 2.4, 4.1) window by window, and
+the injection-recovery depths star by star.
 """
 from __future__ import annotations
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -68,3 +73,90 @@ def test_long_transits_need_a_longer_window():
     three_h, _ = inj.run("tess", 200, depths=(1000,), methods=default)
     assert short["umi_default"][1000] > 2 * long_["umi_default"][1000]
     assert short["umi_default"][1000] > 2 * three_h["umi_default"][1000]
+
+
+# --------------------------------------------------------------------------
+# The HIP path against the FP64 oracle on the same seeded inputs
+
+TREND_TOL = 1e-5  # relative trend tolerance of the estimate against the oracle
+
+
+def _threads():
+    import os
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(16, int(n or 1)))
+
+
+def test_white_noise_bias_gpu_equals_oracle(oracle_lib):
+    """Sections 2.4 and 4.1 on the HIP path: 40,000 independent full windows
+    of white noise (W = 361, 5 iterations, sigma = 1000 ppm) give, window by
+    window, the oracle's trend within the trend tolerance, and therefore mean
+    offsets that agree within TREND_TOL / sigma (trends are about 1) and sit
+    at the Monte-Carlo values within their error bars."""
+    import torch
+
+    import synth
+    from paper_2604_06602_amd import _lib
+    from tests import whitenoise as wn
+    sigma = 1e-3
+    flux, time, idx = synth.white_noise_windows(wn.BIAS_WINDOWS, 361, sigma)
+    f = torch.from_numpy(flux).cuda()
+    t = torch.from_numpy(time).cuda()
+    per = {}
+
+    def gpu_at(fl, tm, W, ix, a, c):
+        tr, _ = _lib.detrend(f, t, W, alpha=a, c=c)
+        g = tr.cpu().numpy()[ix].astype(np.float64)
+        o, _ = oracle_lib.detrend_at(fl, tm, W, ix, alpha=a, c=c)
+        per[a] = (g, o)
+        return g
+    got = wn.bias_offsets(gpu_at)
+    for a, (g, o) in per.items():
+        rel = np.abs(g - o) / np.abs(o)
+        assert rel.max() <= TREND_TOL, (a, rel.max())
+        assert abs(g.mean() - o.mean()) / sigma <= TREND_TOL * np.abs(o).max() / sigma
+    wn.assert_offsets_match(got)
+
+
+def _oracle_detrend(oracle_lib):
+    def detrend(flux, time, lengths, W, alpha, c, scale):
+        tr, _ = oracle_lib.detrend_batch(flux, time, lengths, W, alpha=alpha, c=c, scale=scale,
+                                         n_threads=_threads())
+        return flux.astype(np.float64) / tr
+    return detrend
+
+
+@pytest.mark.parametrize("mission,stars,depths", [("kepler", 48, (5, 50, 100, 200, 500, 1000)),
+                                                  ("tess", 12, (100, 1000))])
+def test_injection_recovery_gpu_equals_oracle(oracle_lib, mission, stars, depths):
+    """Section 3.2 protocol, star by star: the depth each setting recovers
+    from the HIP path's detrended flux (float32 flux / trend) equals the one
+    recovered from the oracle's (float64) within what the trend tolerance
+    allows.  With every detrended value within e = TREND_TOL + 2^-23 of the
+    oracle's, relative, the out-of-transit and in-transit means move by at
+    most e * max|d|, and the depth (B - I) / B by at most 2 e max|d| / B."""
+    from paper_2604_06602_amd import injection as inj
+    ora = _oracle_detrend(oracle_lib)
+    eps = TREND_TOL + 2.0 ** -23
+    for d in depths:
+        flux, time, lengths, Ws, masks = inj._batch(mission, stars, d)
+        off = np.concatenate([[0], np.cumsum(lengths)])
+        for name, p in inj.METHODS.items():
+            g = inj._gpu_detrend(flux, time, lengths, Ws, p["alpha"], p["c"], p["scale"])
+            o = ora(flux, time, lengths, Ws, p["alpha"], p["c"], p["scale"])
+            for i, m in enumerate(masks):
+                gi, oi = g[off[i]:off[i + 1]], o[off[i]:off[i + 1]]
+                assert np.array_equal(np.isnan(gi), np.isnan(oi)), (mission, d, name, i)
+                dg, do = inj.recovered_depth(gi, m), inj.recovered_depth(oi, m)
+                ok = np.isfinite(oi)
+                base = float(oi[ok & ~m].mean())
+                bound = 2 * eps * float(np.abs(oi[ok]).max()) / base
+                assert abs(dg - do) <= bound, (mission, d, name, i, dg, do, bound)
+                pe_g, pe_o = inj.percent_error(dg, d), inj.percent_error(do, d)
+                assert abs(pe_g - pe_o) <= bound / (d * 1e-6) * 100 * (1 + 1e-9)
+    # and run() itself, the harness entry point, with either detrender
+    tg, _ = inj.run(mission, 4, depths=depths[-1:])
+    to, _ = inj.run(mission, 4, depths=depths[-1:], detrend=ora)
+    for name in inj.METHODS:
+        assert abs(tg[name][depths[-1]] - to[name][depths[-1]]) <= \
+            2.2 * eps / (depths[-1] * 1e-6) * 100, (mission, name)

@@ -84,13 +84,17 @@ def test_table4_presets_mixed_in_one_batch(torch, umi, oracle_lib):
     g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, alpha=alphas, c=cs)
     o_tr, o_md = oracle_lib.detrend_batch(b.flux, b.time, b.lengths, b.W, alpha=alphas, c=cs)
     assert_parity(g_tr, g_md, o_tr, o_md, what="per-curve presets")
-    # each curve equals that curve run alone with its own scalar pair
+    # each curve equals that curve run alone with its own scalar pair, bit
+    # for bit at one tile size
+    fixed = umi.LaunchOptions(tile=1024)
+    f_tr, _ = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, alpha=alphas, c=cs,
+                        launch=fixed)
     off = b.offsets
     for ci in [0, 1, 2, 3]:
         f, t, W = b.curve(ci)
         a_tr, _ = run_batch(torch, umi, f, t, [f.size], [W], alpha=float(alphas[ci]),
-                            c=float(cs[ci]))
-        assert np.array_equal(a_tr.view(np.uint32), g_tr[off[ci]:off[ci] + f.size].view(np.uint32))
+                            c=float(cs[ci]), launch=fixed)
+        assert np.array_equal(a_tr.view(np.uint32), f_tr[off[ci]:off[ci] + f.size].view(np.uint32))
 
 
 def test_detrended_flux(torch, umi, oracle_lib):

@@ -273,11 +273,13 @@ def test_no_time_array(torch, umi, oracle_lib):
 
 
 def test_modes_tiles_and_repeats_are_bit_identical(torch, umi):
+    """Tiles above 256 positions (one lane per window) give the same bits
+    whatever their size, launch mode or workgroup count."""
     b = synth.lightcurves.pack([synth.curve_for(3, i) for i in range(10)])
-    ref = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W)
-    variants = [umi.LaunchOptions(mode=umi.MODE_PER_CURVE),
+    ref = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, launch=umi.LaunchOptions(tile=1536))
+    variants = [umi.LaunchOptions(mode=umi.MODE_PER_CURVE, tile=1536),
                 umi.LaunchOptions(tile=300), umi.LaunchOptions(tile=1000, groups_per_cu=1),
-                None]
+                umi.LaunchOptions(tile=512), umi.LaunchOptions(tile=257)]
     for lo in variants:
         out = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, launch=lo)
         assert np.array_equal(out[0].view(np.uint32), ref[0].view(np.uint32)), lo
@@ -285,10 +287,83 @@ def test_modes_tiles_and_repeats_are_bit_identical(torch, umi):
 
 
 def test_curve_alone_equals_curve_in_batch(torch, umi):
+    """With one tile size a curve gives the same bits alone and in a batch;
+    with the library's own choice (a lone curve takes split tiles, a batch
+    does not) the results agree within the trend tolerance, and the medians
+    and the NaN pattern exactly."""
     b = synth.lightcurves.pack([synth.curve_for(3, i) for i in range(6)])
-    g_tr, _ = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W)
+    fixed = umi.LaunchOptions(tile=1024)
+    g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, launch=fixed)
+    a_tr_all, a_md_all = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W)
     off = b.offsets
     for ci in [0, 3, 5]:
         f, t, W = b.curve(ci)
-        a_tr, _ = run_batch(torch, umi, f, t, [f.size], [W])
-        assert np.array_equal(a_tr.view(np.uint32), g_tr[off[ci]:off[ci] + f.size].view(np.uint32))
+        sl = slice(off[ci], off[ci] + f.size)
+        a_tr, a_md = run_batch(torch, umi, f, t, [f.size], [W], launch=fixed)
+        assert np.array_equal(a_tr.view(np.uint32), g_tr[sl].view(np.uint32))
+        s_tr, s_md = run_batch(torch, umi, f, t, [f.size], [W])   # the library's choice
+        assert np.array_equal(s_md.view(np.uint32), a_md_all[sl].view(np.uint32))
+        assert np.array_equal(np.isnan(s_tr), np.isnan(a_tr_all[sl]))
+        ok = ~np.isnan(s_tr)
+        rel = np.abs(s_tr[ok].astype(np.float64) - a_tr_all[sl][ok]) / np.abs(a_tr_all[sl][ok])
+        assert rel.max() <= REL_TOL
+
+
+# ---------------------------------------------------------------------------
+# Split windows: tiles of at most 256 positions share each window between 2,
+# 4 or 8 lanes whose partial sums meet in a DPP / ds_swizzle butterfly.
+
+SPLIT_TILES = [256, 128, 64, 37]   # 2, 4, 8 and 8 lanes per window (37: a ragged tile)
+
+
+@pytest.mark.parametrize("tile", SPLIT_TILES)
+def test_split_windows_edge_cases_against_oracle(torch, umi, oracle_lib, tile):
+    packed = edge_case_batch()
+    mag = window_magnitude(packed.flux, packed.time, packed.lengths, packed.W, oracle_lib)
+    for a, c, it in [(2.0, 5.0, 5), (1.0, 5.0, 3), (10.0, 2.5, 5), (3.0, 5.0, 0)]:
+        g_tr, g_md = run_batch(torch, umi, packed.flux, packed.time, packed.lengths, packed.W,
+                               launch=umi.LaunchOptions(tile=tile), alpha=a, c=c, iters=it)
+        o_tr, o_md = oracle_lib.detrend_batch(packed.flux, packed.time, packed.lengths, packed.W,
+                                              alpha=a, c=c, iters=it)
+        assert_parity(g_tr, g_md, o_tr, o_md, scale=mag,
+                      what="split tile %d a=%g c=%g it=%d" % (tile, a, c, it))
+
+
+@pytest.mark.parametrize("tile", [256, 64])
+def test_split_windows_config_subsets(torch, umi, oracle_lib, tile):
+    ids = [i for i in range(60) if synth.curve_for(3, i)[0].size < 15000][:8]
+    b = synth.lightcurves.pack([synth.curve_for(3, i) for i in ids] +
+                               [synth.curve_for(2, 0), synth.curve_config0()])
+    g_tr, g_md = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W,
+                           launch=umi.LaunchOptions(tile=tile))
+    o_tr, o_md = oracle_lib.detrend_batch(b.flux, b.time, b.lengths, b.W)
+    assert_parity(g_tr, g_md, o_tr, o_md, what="split tile %d subsets" % tile)
+
+
+def test_split_windows_are_deterministic_and_close_to_one_lane(torch, umi):
+    b = synth.lightcurves.pack([synth.curve_for(3, i) for i in range(5)])
+    one = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, launch=umi.LaunchOptions(tile=1536))
+    ok = ~np.isnan(one[0])
+    for tile in [256, 128, 64]:
+        lo = umi.LaunchOptions(tile=tile)
+        first = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W, launch=lo)
+        again = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W,
+                          launch=umi.LaunchOptions(tile=tile, mode=umi.MODE_PER_CURVE))
+        assert np.array_equal(first[0].view(np.uint32), again[0].view(np.uint32)), tile
+        assert np.array_equal(first[1].view(np.uint32), one[1].view(np.uint32)), tile
+        assert np.array_equal(np.isnan(first[0]), ~ok)
+        rel = np.abs(first[0][ok].astype(np.float64) - one[0][ok]) / np.abs(one[0][ok])
+        assert rel.max() <= REL_TOL, (tile, rel.max())
+
+
+def test_lone_curve_takes_split_tiles(torch, umi, oracle_lib):
+    """The small-batch rule: one 20,000-sample curve is cut into tiles of 64
+    positions (eight lanes per window) -- the results equal an explicit
+    64-position launch bit for bit -- and match the oracle."""
+    flux, time, W = synth.curve_config0()
+    umi.set_tuning(None)   # the built-in rule, whatever table an earlier test loaded
+    auto = run_batch(torch, umi, flux, time, [flux.size], [W])
+    forced = run_batch(torch, umi, flux, time, [flux.size], [W], launch=umi.LaunchOptions(tile=64))
+    assert np.array_equal(auto[0].view(np.uint32), forced[0].view(np.uint32))
+    o_tr, o_md = oracle_lib.detrend(flux, time, W)
+    assert_parity(auto[0], auto[1], o_tr, o_md, what="lone curve, library tiles")

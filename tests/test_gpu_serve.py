@@ -2,9 +2,10 @@
 
 Curves drawn like the mixed workload arrive while earlier ones run, each
 with one of the Table 4 (alpha, c) settings, so steps mix them; every result
-must be bit-identical to the same curve run alone through the C ABI with its
-own setting, and sampled positions must match the FP64 oracle (trend at
-1e-5 relative).
+must equal the same curve run alone through the C ABI with its own setting
+within the trend tolerance (1e-5 relative; a lone curve may split its
+windows over several lanes, which orders the sums differently), and sampled
+positions must match the FP64 oracle (trend at 1e-5 relative).
 """
 from __future__ import annotations
 
@@ -54,7 +55,14 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
         td = torch.from_numpy(t).cuda()
         alone, _ = umi.detrend(fd, td, W, alpha=a, c=c)
         torch.cuda.synchronize()
-        assert np.array_equal(alone.cpu().numpy().view(np.uint32), res.view(np.uint32))
+        alone = alone.cpu().numpy()
+        # a lone curve takes split tiles (several lanes per window), a crowded
+        # step may not: the same within the trend tolerance, NaNs identical
+        assert np.array_equal(np.isnan(alone), np.isnan(res))
+        ok = ~np.isnan(res)
+        if ok.any():
+            rel = np.abs(alone[ok].astype(np.float64) - res[ok]) / np.abs(res[ok])
+            assert rel.max() <= 1e-5
     for (f, t, W, a, c), res in list(zip(curves, results))[:8]:
         idx = np.unique(rng.integers(0, f.size, 40))
         o_tr, _ = oracle_lib.detrend_at(f, t, W, idx, alpha=a, c=c)
@@ -86,3 +94,24 @@ def test_copy_async_round_trip(torch):
     s.synchronize()
     assert torch.equal(back, host)
     assert not dev[total:].any().item()
+
+
+def test_executor_device_memory_stays_within_its_budget(torch):
+    """The serving executor's arrays plus the plan workspace that
+    umi_plan_create allocates hold at most BYTES_PER_SAMPLE per sample of the
+    arena (measured as the drop in free device memory; torch's allocator
+    rounds each array up to 2 MiB)."""
+    from paper_2604_06602_amd.serve import BYTES_PER_SAMPLE, GpuExecutor
+    budget = 2 << 30
+    capacity = budget // BYTES_PER_SAMPLE
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    ex = GpuExecutor(capacity, max_curves=4096, max_W=721, staging_bytes=64 << 20)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    used = free0 - free1
+    ex.close()
+    del ex
+    assert used <= budget + 3 * (2 << 20) + (1 << 20), (used, budget)
+    assert used >= capacity * (BYTES_PER_SAMPLE - 1)  # the estimate is not loose either

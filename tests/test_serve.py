@@ -120,6 +120,35 @@ def test_oversize_and_invalid_requests_are_rejected():
     assert s["rejected"] == 3
 
 
+def test_parameters_that_break_float32_fail_only_their_request():
+    """alpha or c that are infinite, or overflow or flush to zero as float32
+    (the kernels' type), are rejected at submit; a step that the C ABI would
+    reject as a whole never forms, so valid requests of the same burst run."""
+    class CheckingExecutor(FakeExecutor):
+        def launch(self, offsets, lengths, Ws, alphas, cs, iters, uploads, ranges):
+            for a, c in zip(alphas, cs):  # the C ABI's finite_pos on float32
+                a32, c32 = np.float32(a), np.float32(c)
+                if not (np.isfinite(a32) and a32 > 0 and np.isfinite(c32) and c32 > 0):
+                    raise RuntimeError("UMI_ERR_INVALID_ARG: per-curve alpha/c")
+            return super().launch(offsets, lengths, Ws, alphas, cs, iters, uploads, ranges)
+    srv = Server(CheckingExecutor(100000, delay=0.02))
+    bad = [dict(alpha=float("inf")), dict(c=float("inf")), dict(alpha=1e39), dict(c=1e-50),
+           dict(alpha=float("nan")), dict(iters=-1), dict(iters=2.5)]
+    futs = []
+    for i in range(len(bad)):
+        futs.append(("ok", srv.submit(np.ones(100, np.float32), W=5)))
+        futs.append(("bad", srv.submit(np.ones(100, np.float32), W=5, **bad[i])))
+    for kind, fu in futs:
+        if kind == "ok":
+            assert fu.result(timeout=5)[0] == 2.0
+        else:
+            with pytest.raises(ValueError):
+                fu.result(timeout=5)
+    s = srv.summary()
+    srv.close()
+    assert s["rejected"] == len(bad) and s["completed"] == len(bad) and s["failed"] == 0
+
+
 def test_cancelled_request_never_runs():
     gate = threading.Event()
 
