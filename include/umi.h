@@ -238,6 +238,45 @@ umi_status umi_plan_run_ex(umi_plan* plan, const int64_t* offsets,
                            int32_t iters, const umi_options* options);
 umi_status umi_plan_destroy(umi_plan* plan);
 
+/*
+ * umi_detrend_batch_noalloc -- umi_detrend_batch for callers that cannot
+ * allocate memory during the call: code under hipGraph stream capture, tight
+ * serving loops, and harnesses that forbid hipMalloc.  Same arguments, layout,
+ * results (bit for bit, given the same launch options) and errors as
+ * umi_detrend_batch; only the workspace differs.
+ *
+ * The workspace -- the staged header and curve table, the queue counter, the
+ * tile list and one segment word per sample -- lives in a static device array
+ * of UMI_NOALLOC_SCRATCH_BYTES (about 72 MiB) that each GPU the library runs
+ * on holds from the first call on that GPU until the process ends.  A call
+ * allocates no device, pinned or host memory on its way to the launches (the
+ * curve table is packed into static host arrays and copied with
+ * hipMemcpyAsync from pageable memory; only an error message is built on the
+ * heap); it looks up the array's device address once per GPU, on that GPU's
+ * first call.
+ *
+ * Limits (larger batches give UMI_ERR_UNSUPPORTED and enqueue nothing):
+ *   sum(lengths) <= UMI_NOALLOC_MAX_SAMPLES, n_curves <= UMI_NOALLOC_MAX_CURVES,
+ *   and the batch's tiles <= UMI_NOALLOC_MAX_TILES (only windows close to
+ *   UMI_MAX_WINDOW, whose tiles are a few positions wide, reach this).
+ *
+ * Every call on a GPU uses that GPU's one array, whatever the stream, and
+ * leaves the last batch's contents there (the kernels overwrite every part
+ * they read, and the pre-pass clears the queue counter).  Calls on one stream
+ * are ordered by the stream; calls on one GPU whose stream work can overlap
+ * (different streams, or several threads) race on the array and give
+ * undefined results.  Host-side, concurrent calls are serialised by a lock.
+ */
+#define UMI_NOALLOC_MAX_SAMPLES 16777216 /* 2^24 samples per call */
+#define UMI_NOALLOC_MAX_CURVES 8192
+#define UMI_NOALLOC_MAX_TILES 1048576    /* 2^20 tiles per call */
+#define UMI_NOALLOC_SCRATCH_BYTES 75825664
+umi_status umi_detrend_batch_noalloc(const float* flux, const double* time,
+                                     const int64_t* lengths, int64_t n_curves,
+                                     const int32_t* W, float alpha, float c,
+                                     int32_t iters, float* trend, float* median,
+                                     const umi_launch* launch, void* stream);
+
 /* Window-size rule of Section 2: round(window_days / cadence_days) | 1.
  * Returns -1 when either argument is not positive and finite. */
 int32_t umi_window_from_cadence(double cadence_days, double window_days);

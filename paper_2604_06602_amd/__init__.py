@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     detrend,
     detrend_batch,
     detrend_batch_into,
+    detrend_batch_noalloc_into,
     detrend_gather_into,
     host_copy_many,
     copy_async,

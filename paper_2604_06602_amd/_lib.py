@@ -72,6 +72,10 @@ def _load():
     lib.umi_detrend_batch.argtypes = [_vp, _vp, _i64p, ctypes.c_int64, _i32p, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_int32, _vp, _vp,
                                       ctypes.POINTER(Launch), _vp]
+    lib.umi_detrend_batch_noalloc.restype = ctypes.c_int
+    lib.umi_detrend_batch_noalloc.argtypes = [_vp, _vp, _i64p, ctypes.c_int64, _i32p,
+                                              ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                              _vp, _vp, ctypes.POINTER(Launch), _vp]
     lib.umi_detrend_gather.restype = ctypes.c_int
     lib.umi_detrend_gather.argtypes = [_vp, _vp, _i64p, _i64p, ctypes.c_int64, _i32p,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp, _vp,
@@ -284,6 +288,31 @@ def detrend_batch_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=
                                        int(iters), op, mp, ctypes.byref(opts), lp,
                                        _stream_handle(stream))
     del keep
+    _check(st)
+
+
+NOALLOC_MAX_SAMPLES = 1 << 24
+NOALLOC_MAX_CURVES = 8192
+NOALLOC_MAX_TILES = 1 << 20
+
+
+def detrend_batch_noalloc_into(flux, time, lengths, W, trend, median=None, alpha=2.0, c=5.0,
+                               iters=5, launch: LaunchOptions | None = None, stream=None):
+    """umi_detrend_batch_noalloc on preallocated device tensors: the packed
+    batch call whose workspace is the library's static device array (at most
+    NOALLOC_MAX_SAMPLES samples and NOALLOC_MAX_CURVES curves per call)."""
+    torch = _torch()
+    lengths = np.ascontiguousarray(lengths, dtype=np.int64)
+    Wa = np.ascontiguousarray(np.broadcast_to(np.asarray(W, dtype=np.int32), lengths.shape))
+    n = int(lengths.sum()) if lengths.size else 0
+    lp = ctypes.byref(launch.as_struct()) if launch is not None else None
+    st = lib.umi_detrend_batch_noalloc(_dev_ptr(flux, torch.float32, "flux", n),
+                                       _dev_ptr(time, torch.float64, "time", n),
+                                       lengths.ctypes.data_as(_i64p), lengths.size,
+                                       Wa.ctypes.data_as(_i32p), float(alpha), float(c),
+                                       int(iters), _dev_ptr(trend, torch.float32, "trend", n),
+                                       _dev_ptr(median, torch.float32, "median", n), lp,
+                                       _stream_handle(stream))
     _check(st)
 
 

@@ -731,6 +731,141 @@ void plan_free(umi_plan* p)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// The allocation-free batch call (umi_detrend_batch_noalloc): the workspace
+// of a batch -- header and curve table, queue counter, tile list, segment
+// words -- lives in one file-scope device array, and the host side packs into
+// static arrays.  Nothing is allocated per call, on the device or the host.
+
+namespace umi {
+namespace noalloc {
+
+constexpr int64_t kMaxSamples = UMI_NOALLOC_MAX_SAMPLES;
+constexpr int64_t kMaxCurves = UMI_NOALLOC_MAX_CURVES;
+constexpr int64_t kMaxTiles = UMI_NOALLOC_MAX_TILES;
+constexpr size_t kAlign = 256;
+constexpr size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// byte offsets inside the scratch array
+constexpr size_t kBlockOff = 0;  // BatchHeader + curve table
+constexpr size_t kCounterOff = round_up(sizeof(BatchHeader) + kMaxCurves * sizeof(CurveDesc));
+constexpr size_t kTilesOff = kCounterOff + kAlign;
+constexpr size_t kSegidOff = round_up(kTilesOff + kMaxTiles * sizeof(int2));
+constexpr size_t kScratchBytes = kSegidOff + kMaxSamples * sizeof(int32_t);
+static_assert(kScratchBytes == UMI_NOALLOC_SCRATCH_BYTES, "scratch size in umi.h");
+
+constexpr int kMaxDevices = 64;
+
+}  // namespace noalloc
+}  // namespace umi
+
+// Each GPU the library runs on holds its own copy of this array for the life
+// of the process.  Its name is a host-side stand-in: host code uses only the
+// device address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[umi::noalloc::kScratchBytes];
+
+namespace umi {
+namespace noalloc {
+
+std::mutex g_mu;                      // guards everything below
+uint8_t* g_dev_scratch[kMaxDevices];  // device address of `scratch` per device
+// host-side packing arrays (no allocation per call)
+int64_t g_off[kMaxCurves];
+CurveDesc g_curves[kMaxCurves];
+int64_t g_curve_tiles[kMaxCurves];
+int g_tile_of[kMaxCurves];
+int32_t g_order[kMaxCurves];
+alignas(16) uint8_t g_block[kCounterOff];
+
+// The device address of `scratch` on `device` (current), looked up once.
+hipError_t scratch_for(int device, uint8_t** out)
+{
+    if (!g_dev_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_dev_scratch[device] = static_cast<uint8_t*>(ptr);
+    }
+    *out = g_dev_scratch[device];
+    return hipSuccess;
+}
+
+umi_status detrend_batch(const float* flux, const double* time, const int64_t* lengths,
+                         int64_t n_curves, const int32_t* W, float alpha, float c, int32_t iters,
+                         float* trend, float* median, const umi_launch* launch,
+                         hipStream_t stream)
+{
+    umi_status st;
+    if (take_injected(&st)) return st;
+    if (n_curves < 0) return fail(UMI_ERR_INVALID_ARG, "n_curves must be >= 0");
+    if (n_curves == 0) return UMI_OK;
+    if (!lengths || !W) return fail(UMI_ERR_INVALID_ARG, "lengths and W must not be NULL");
+    if (n_curves > kMaxCurves)
+        return fail(UMI_ERR_UNSUPPORTED,
+                    "umi_detrend_batch_noalloc: more than UMI_NOALLOC_MAX_CURVES curves");
+    umi_launch opt;
+    if ((st = check_launch(launch, &opt)) != UMI_OK) return st;
+    if ((st = check_params(alpha, c, iters)) != UMI_OK) return st;
+    int64_t total = 0;
+    for (int64_t b = 0; b < n_curves; ++b) {
+        if (lengths[b] < 0) return fail(UMI_ERR_INVALID_ARG, "curve lengths must be >= 0");
+        if ((st = check_window(W[b])) != UMI_OK) return st;
+        if (lengths[b] > kMaxSamples - total)
+            return fail(UMI_ERR_UNSUPPORTED,
+                        "umi_detrend_batch_noalloc: more than UMI_NOALLOC_MAX_SAMPLES samples");
+        total += lengths[b];
+    }
+    if (total == 0) return UMI_OK;
+    if (!flux || !trend) return fail(UMI_ERR_INVALID_ARG, "flux and trend must not be NULL");
+
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (device < 0 || device >= kMaxDevices)
+        return fail(UMI_ERR_UNSUPPORTED, "umi_detrend_batch_noalloc: device index above 63");
+    const int n_cu = cu_count(device);
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base = nullptr;
+    if ((e = scratch_for(device, &base)) != hipSuccess)
+        return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    int64_t acc = 0;
+    for (int64_t b = 0; b < n_curves; ++b) {
+        g_off[b] = acc;
+        acc += lengths[b];
+    }
+    const umi_options o{nullptr, nullptr, UMI_SCALE_UPPER_RMS, 0, nullptr, nullptr};
+    PackView v{g_curves, g_curve_tiles, g_tile_of, g_order};
+    if ((st = pack_into(g_off, lengths, n_curves, W, alpha, c, o, opt, n_cu, kMaxTiles, &v)) !=
+        UMI_OK)
+        return st;
+    if (v.ntiles > kMaxTiles)
+        return fail(UMI_ERR_UNSUPPORTED,
+                    "umi_detrend_batch_noalloc: the batch needs more than UMI_NOALLOC_MAX_TILES "
+                    "tiles (very wide windows cut curves into small tiles)");
+    write_block(g_block, g_curves, v.ncurves, v.ntiles, iters, o, time);
+    // from pageable host memory: the source is free again once the call returns
+    if ((e = hipMemcpyAsync(base + kBlockOff, g_block, block_bytes(v.ncurves),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return fail_hip(e, "curve table copy");
+    DeviceBuffers b;  // a view of the scratch array; never released
+    b.segid = reinterpret_cast<int32_t*>(base + kSegidOff);
+    b.cap_segid = kMaxSamples;
+    b.tiles = reinterpret_cast<int2*>(base + kTilesOff);
+    b.cap_tiles = kMaxTiles;
+    b.counter = reinterpret_cast<uint32_t*>(base + kCounterOff);
+    b.cap_counter = 1;
+    const int grid = (int)std::min<int64_t>(v.ntiles, (int64_t)v.gpc * n_cu);
+    e = enqueue_kernels(flux, time, trend, median, base + kBlockOff, b, opt.mode, g_curves,
+                        g_curve_tiles, (int)v.ncurves, grid, (hipEvent_t)opt.main_start,
+                        (hipEvent_t)opt.main_stop, stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return UMI_OK;
+}
+
+}  // namespace noalloc
+}  // namespace umi
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 extern "C" {
@@ -760,6 +895,15 @@ umi_status umi_detrend_batch(const float* flux, const double* time, const int64_
     }
     return umi::detrend_gather(flux, time, off.data(), lengths, n_curves, W, alpha, c, iters,
                                trend, median, nullptr, launch, static_cast<hipStream_t>(stream));
+}
+
+umi_status umi_detrend_batch_noalloc(const float* flux, const double* time,
+                                     const int64_t* lengths, int64_t n_curves, const int32_t* W,
+                                     float alpha, float c, int32_t iters, float* trend,
+                                     float* median, const umi_launch* launch, void* stream)
+{
+    return umi::noalloc::detrend_batch(flux, time, lengths, n_curves, W, alpha, c, iters, trend,
+                                       median, launch, static_cast<hipStream_t>(stream));
 }
 
 umi_status umi_detrend_gather(const float* flux, const double* time, const int64_t* offsets,

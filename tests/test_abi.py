@@ -325,3 +325,38 @@ def test_host_copy_many_with_many_small_copies(lib):
     perm = rng.permutation(n)  # scatter the copies in a shuffled order
     lib.host_copy_many(dst.ctypes.data + offs[perm], src.ctypes.data + offs[perm], sizes[perm], 8)
     assert np.array_equal(dst, src)
+
+
+def _raw_noalloc(lib, lengths, W, flux=1, trend=1):
+    lengths = np.asarray(lengths, np.int64)
+    Wa = np.asarray(W, np.int32)
+    return lib.lib.umi_detrend_batch_noalloc(
+        ctypes.c_void_p(flux) if flux else None, None,
+        lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), lengths.size,
+        Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 2.0, 5.0, 5,
+        ctypes.c_void_p(trend) if trend else None, None, None, None)
+
+
+def test_noalloc_limits_and_validation_without_device(lib):
+    """The allocation-free call checks its fixed limits, and the arguments the
+    batch call checks, on the host before it touches the device."""
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define (UMI_NOALLOC_\w+) (\d+)", text))
+    assert int(consts["UMI_NOALLOC_MAX_SAMPLES"]) == lib.NOALLOC_MAX_SAMPLES
+    assert int(consts["UMI_NOALLOC_MAX_CURVES"]) == lib.NOALLOC_MAX_CURVES
+    assert int(consts["UMI_NOALLOC_MAX_TILES"]) == lib.NOALLOC_MAX_TILES
+    big = lib.NOALLOC_MAX_SAMPLES
+    assert _raw_noalloc(lib, [big, 1], [25, 25]) == lib.UMI_ERR_UNSUPPORTED
+    assert "UMI_NOALLOC_MAX_SAMPLES" in lib.last_error()
+    assert _raw_noalloc(lib, [2**62, 2**62], [25, 25]) == lib.UMI_ERR_UNSUPPORTED  # no overflow
+    n = lib.NOALLOC_MAX_CURVES + 1
+    assert _raw_noalloc(lib, [1] * n, [25] * n) == lib.UMI_ERR_UNSUPPORTED
+    assert "UMI_NOALLOC_MAX_CURVES" in lib.last_error()
+    assert _raw_noalloc(lib, [10], [4]) == lib.UMI_ERR_INVALID_ARG
+    assert _raw_noalloc(lib, [-1], [5]) == lib.UMI_ERR_INVALID_ARG
+    assert _raw_noalloc(lib, [10], [5], flux=0) == lib.UMI_ERR_INVALID_ARG
+    assert _raw_noalloc(lib, [10], [5], trend=0) == lib.UMI_ERR_INVALID_ARG
+    assert _raw_noalloc(lib, [], []) == lib.UMI_OK
+    assert _raw_noalloc(lib, [0, 0], [5, 7], flux=0, trend=0) == lib.UMI_OK
+    lib.debug_inject_error(lib.UMI_ERR_DEVICE)
+    assert _raw_noalloc(lib, [0], [5]) == lib.UMI_ERR_DEVICE
