@@ -245,9 +245,10 @@ umi_status umi_plan_destroy(umi_plan* plan);
  * results (bit for bit, given the same launch options) and errors as
  * umi_detrend_batch; only the workspace differs.
  *
- * The workspace -- the staged header and curve table, the queue counter, the
- * tile list and one segment word per sample -- lives in a static device array
- * of UMI_NOALLOC_SCRATCH_BYTES (about 72 MiB) that each GPU the library runs
+ * The workspace -- the staged header and curve table, the queue and pre-pass
+ * counters, the pre-pass chunk records, the tile list and one segment word
+ * per sample -- lives in a static device array
+ * of UMI_NOALLOC_SCRATCH_BYTES (about 74 MiB) that each GPU the library runs
  * on holds from the first call on that GPU until the process ends.  A call
  * allocates no device, pinned or host memory on its way to the launches (the
  * curve table is packed into static host arrays and copied with
@@ -262,7 +263,9 @@ umi_status umi_plan_destroy(umi_plan* plan);
  *
  * Every call on a GPU uses that GPU's one array, whatever the stream, and
  * leaves the last batch's contents there (the kernels overwrite every part
- * they read, and the pre-pass clears the queue counter).  Calls on one stream
+ * they read before reading it; the pre-pass's ticket counters return to zero
+ * at the end of each call, and its chunk records carry a launch count that
+ * tells them from an earlier call's).  Calls on one stream
  * are ordered by the stream; calls on one GPU whose stream work can overlap
  * (different streams, or several threads) race on the array and give
  * undefined results.  Host-side, concurrent calls are serialised by a lock.
@@ -270,7 +273,7 @@ umi_status umi_plan_destroy(umi_plan* plan);
 #define UMI_NOALLOC_MAX_SAMPLES 16777216 /* 2^24 samples per call */
 #define UMI_NOALLOC_MAX_CURVES 8192
 #define UMI_NOALLOC_MAX_TILES 1048576    /* 2^20 tiles per call */
-#define UMI_NOALLOC_SCRATCH_BYTES 75825664
+#define UMI_NOALLOC_SCRATCH_BYTES 78250496
 umi_status umi_detrend_batch_noalloc(const float* flux, const double* time,
                                      const int64_t* lengths, int64_t n_curves,
                                      const int32_t* W, float alpha, float c,

@@ -26,8 +26,9 @@
 namespace umi {
 
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
-                          int2* tiles, uint32_t* counter, hipStream_t stream);
+                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
+                          int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
+                          hipStream_t stream);
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
                        int tile_count, uint32_t* counter, int grid, float* trend, float* median,
@@ -212,6 +213,7 @@ struct PackView {
     int32_t* order;           // scratch: input index per table entry
     int64_t ncurves = 0;      // entries written
     int64_t ntiles = 0;
+    int64_t nchunks = 0;      // pre-pass chunks
     int gpc = kDefaultGroupsPerCU;  // persistent groups per CU
 };
 
@@ -272,11 +274,15 @@ umi_status pack_into(const int64_t* offsets, const int64_t* lengths, int64_t n, 
     });
     out->ncurves = nord;
     out->ntiles = 0;
+    out->nchunks = 0;
     for (int64_t i = 0; i < nord; ++i) {
         const int32_t b = order[i];
         const int64_t nt = (lengths[b] + tile_of[b] - 1) / tile_of[b];
+        const int64_t nch = (lengths[b] + kPrepChunk - 1) / kPrepChunk;
         if (out->ntiles + nt > (int64_t)INT32_MAX)
             return fail(UMI_ERR_UNSUPPORTED, "too many tiles in one batch");
+        if (out->nchunks + nch > (int64_t)INT32_MAX)
+            return fail(UMI_ERR_UNSUPPORTED, "too many samples in one batch");
         CurveDesc& d = out->curves[i];
         d.off = offsets[b];
         d.len = (int32_t)lengths[b];
@@ -286,8 +292,11 @@ umi_status pack_into(const int64_t* offsets, const int64_t* lengths, int64_t n, 
         d.alpha = o.alpha ? o.alpha[b] : alpha;
         d.c = o.c ? o.c[b] : c;
         d.window_days = o.window_days ? o.window_days[b] : 0.0;
+        d.chunk_base = (int32_t)out->nchunks;
+        d.reserved = 0;
         out->curve_tiles[i] = nt;
         out->ntiles += nt;
+        out->nchunks += nch;
     }
     out->gpc = kDefaultGroupsPerCU;
     if (nord > 0) {
@@ -303,6 +312,7 @@ struct Packed {
     std::vector<CurveDesc> curves;
     std::vector<int64_t> curve_tiles;
     int64_t ntiles = 0;
+    int64_t nchunks = 0;
     int gpc = kDefaultGroupsPerCU;
 };
 
@@ -320,6 +330,7 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
     out->curves.resize((size_t)v.ncurves);
     out->curve_tiles.resize((size_t)v.ncurves);
     out->ntiles = v.ntiles;
+    out->nchunks = v.nchunks;
     out->gpc = v.gpc;
     return UMI_OK;
 }
@@ -330,11 +341,12 @@ size_t block_bytes(int64_t ncurves)
 }
 
 void write_block(uint8_t* dst, const CurveDesc* curves, int64_t ncurves, int64_t ntiles,
-                 int32_t iters, const umi_options& o, const double* time)
+                 int64_t nchunks, int32_t iters, const umi_options& o, const double* time)
 {
     BatchHeader h = {};
     h.n_curves = (int32_t)ncurves;
     h.n_tiles = (int32_t)ntiles;
+    h.n_chunks = (int32_t)nchunks;
     h.iters = iters;
     h.scale = o.scale;
     h.detrended = o.detrended;
@@ -350,9 +362,10 @@ void write_block(uint8_t* dst, const CurveDesc* curves, int64_t ncurves, int64_t
 // slack so that batches of slowly growing size do not reallocate every call;
 // a plan reserves exactly its fixed capacity once (`exact`).
 template <class T>
-hipError_t grow(T** p, int64_t* cap, int64_t need, bool exact = false)
+hipError_t grow(T** p, int64_t* cap, int64_t need, bool exact = false, bool* fresh = nullptr)
 {
     if (need <= *cap) return hipSuccess;
+    if (fresh) *fresh = true;
     if (*p) {
         hipError_t e = hipFree(*p);
         *p = nullptr;
@@ -370,63 +383,93 @@ struct DeviceBuffers {
     int64_t cap_segid = 0;
     int2* tiles = nullptr;
     int64_t cap_tiles = 0;
-    uint32_t* counter = nullptr;
-    int64_t cap_counter = 0;
+    ChunkRec* recs = nullptr;   // pre-pass chunk records
+    int64_t cap_recs = 0;
+    Counters* ctr = nullptr;    // queue, ticket and epoch counters
+    int64_t cap_ctr = 0;
 
-    hipError_t reserve(int64_t span, int64_t ntiles, bool exact = false)
+    // Zero-filled on allocation (on `stream`, ahead of any kernel there): the
+    // counters, and chunk records whose flags must not look like this epoch's.
+    hipError_t reserve(int64_t span, int64_t ntiles, int64_t nchunks, hipStream_t stream,
+                       bool exact = false)
     {
         hipError_t e;
         if ((e = grow(&segid, &cap_segid, span, exact)) != hipSuccess) return e;
         if ((e = grow(&tiles, &cap_tiles, ntiles, exact)) != hipSuccess) return e;
-        return grow(&counter, &cap_counter, 1, exact);
+        bool fresh_recs = false, fresh_ctr = false;
+        if ((e = grow(&recs, &cap_recs, nchunks, exact, &fresh_recs)) != hipSuccess) return e;
+        if ((e = grow(&ctr, &cap_ctr, 1, true, &fresh_ctr)) != hipSuccess) return e;
+        // a fresh counter restarts the epochs: old records must go too
+        if ((fresh_recs || fresh_ctr) && cap_recs > 0 &&
+            (e = hipMemsetAsync(recs, 0, (size_t)cap_recs * sizeof(ChunkRec), stream)) != hipSuccess)
+            return e;
+        if (fresh_ctr && (e = hipMemsetAsync(ctr, 0, sizeof(Counters), stream)) != hipSuccess)
+            return e;
+        return hipSuccess;
     }
-    bool fits(int64_t span, int64_t ntiles) const
+    bool fits(int64_t span, int64_t ntiles, int64_t nchunks) const
     {
-        return span <= cap_segid && ntiles <= cap_tiles && cap_counter >= 1;
+        return span <= cap_segid && ntiles <= cap_tiles && nchunks <= cap_recs && cap_ctr >= 1;
     }
     // device bytes held
     int64_t bytes() const
     {
         return cap_segid * (int64_t)sizeof(int32_t) + cap_tiles * (int64_t)sizeof(int2) +
-               cap_counter * (int64_t)sizeof(uint32_t);
+               cap_recs * (int64_t)sizeof(ChunkRec) + cap_ctr * (int64_t)sizeof(Counters);
     }
     void release()
     {
         if (segid) (void)hipFree(segid);
         if (tiles) (void)hipFree(tiles);
-        if (counter) (void)hipFree(counter);
+        if (recs) (void)hipFree(recs);
+        if (ctr) (void)hipFree(ctr);
         *this = DeviceBuffers();
     }
 };
 
+// The pre-pass of a batch: the curve walker (one workgroup per curve) for
+// many curves, else the chunked pre-pass over at most kPrepGroupsPerCU
+// workgroups per CU.
+struct PrepLaunch {
+    bool walk;
+    int grid;
+};
+PrepLaunch prep_launch_for(int64_t ncurves, int64_t nchunks, int n_cu)
+{
+    if (ncurves >= kPrepWalkMinCurves) return {true, (int)ncurves};
+    return {false, (int)std::min<int64_t>(nchunks, (int64_t)kPrepGroupsPerCU * n_cu)};
+}
+
 // Enqueue the pre-pass and estimate kernels for a staged block (header +
 // curve table, at `dblock` on the device by the time the stream reaches them).
 // In per-curve mode `table` and `curve_tiles` (host copies of the staged
-// table) give each curve's tile range.
+// table, `ncurves` entries) give each curve's tile range and length.
 hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, float* median,
                            const uint8_t* dblock, const DeviceBuffers& b, int mode,
-                           const CurveDesc* table, const int64_t* curve_tiles, int prep_grid,
-                           int main_grid, hipEvent_t ev0, hipEvent_t ev1, hipStream_t stream)
+                           const CurveDesc* table, const int64_t* curve_tiles, int ncurves,
+                           PrepLaunch prep, int main_grid, hipEvent_t ev0, hipEvent_t ev1,
+                           hipStream_t stream)
 {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblock);
     const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
     hipError_t e;
     if (mode == UMI_MODE_PERSISTENT) {
-        if ((e = launch_prepass(flux, time, hdr, curves, 0, prep_grid, b.segid, b.tiles,
-                                b.counter, stream)) != hipSuccess)
+        if ((e = launch_prepass(flux, time, hdr, curves, -1, prep.grid, b.segid, b.tiles, b.ctr,
+                                b.recs, true, prep.walk, stream)) != hipSuccess)
             return e;
         if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
-        if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, 0, -1, b.counter, main_grid,
+        if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, 0, -1, &b.ctr->queue, main_grid,
                              trend, median, stream)) != hipSuccess)
             return e;
         if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
         return hipSuccess;
     }
-    // one pre-pass and one estimate launch per curve, one workgroup per tile
+    // one pre-pass (the walker, one workgroup) and one estimate launch per
+    // curve, one workgroup per tile
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
-    for (int i = 0; i < prep_grid; ++i) {
-        if ((e = launch_prepass(flux, time, hdr, curves, i, 1, b.segid, b.tiles, nullptr,
-                                stream)) != hipSuccess)
+    for (int i = 0; i < ncurves; ++i) {
+        if ((e = launch_prepass(flux, time, hdr, curves, i, 1, b.segid, b.tiles, b.ctr, b.recs,
+                                false, true, stream)) != hipSuccess)
             return e;
         const int nt = (int)curve_tiles[i];
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, table[i].tile_base, nt, nullptr,
@@ -467,15 +510,16 @@ struct Workspace {
 
     // Make room; if anything must be reallocated, first wait for work already
     // queued on this stream, which may still read the old buffers.
-    hipError_t reserve(int64_t span, int64_t ncurves, int64_t ntiles)
+    hipError_t reserve(int64_t span, int64_t ncurves, int64_t ntiles, int64_t nchunks)
     {
         const int64_t bytes = (int64_t)block_bytes(ncurves);
-        if (buf.fits(span, ntiles) && bytes <= cap_dblock && bytes <= cap_hblock && staged)
+        if (buf.fits(span, ntiles, nchunks) && bytes <= cap_dblock && bytes <= cap_hblock &&
+            staged)
             return hipSuccess;
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
         staged_pending = false;
-        if ((e = buf.reserve(span, ntiles)) != hipSuccess) return e;
+        if ((e = buf.reserve(span, ntiles, nchunks, stream)) != hipSuccess) return e;
         if ((e = grow(&dblock, &cap_dblock, bytes)) != hipSuccess) return e;
         if (bytes > cap_hblock) {
             if (hblock) (void)hipHostFree(hblock);
@@ -559,14 +603,14 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     const int64_t nc = (int64_t)p.curves.size();
     Workspace* ws = workspace_for(device, stream);
     std::lock_guard<std::mutex> lk(ws->mu);
-    if ((e = ws->reserve(span, nc, p.ntiles)) != hipSuccess)
+    if ((e = ws->reserve(span, nc, p.ntiles, p.nchunks)) != hipSuccess)
         return fail_hip(e, "workspace allocation");
     if (ws->staged_pending) {  // the previous copy out of the staging block must be done
         if ((e = hipEventSynchronize(ws->staged)) != hipSuccess)
             return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
-    write_block(ws->hblock, p.curves.data(), nc, p.ntiles, iters, o, time);
+    write_block(ws->hblock, p.curves.data(), nc, p.ntiles, p.nchunks, iters, o, time);
     if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return fail_hip(e, "curve table copy");
@@ -575,8 +619,9 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     ws->staged_pending = true;
     const int grid = (int)std::min<int64_t>(p.ntiles, (int64_t)p.gpc * cu_count(device));
     e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, p.curves.data(),
-                        p.curve_tiles.data(), (int)nc, grid, (hipEvent_t)opt.main_start,
-                        (hipEvent_t)opt.main_stop, stream);
+                        p.curve_tiles.data(), (int)nc,
+                        prep_launch_for(nc, p.nchunks, cu_count(device)), grid,
+                        (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -689,6 +734,7 @@ struct umi_plan {
     int64_t capacity = 0;
     int64_t max_curves = 0;
     int64_t max_tiles = 0;
+    int64_t max_chunks = 0;
     int32_t max_W = 0;
     const float* flux = nullptr;
     const double* time = nullptr;
@@ -697,8 +743,9 @@ struct umi_plan {
     int main_grid = 0;
     umi::DeviceBuffers buf;
     // Two captured graphs per slot: [0] for batches of at most
-    // kPrepWideCurves curves (a pre-pass grid of that many wide workgroups,
-    // and a copy of that much of the table), [1] for up to max_curves.
+    // kPrepSmallChunks pre-pass chunks (the chunked pre-pass over that many
+    // workgroups, and a copy of that much of the table), [1] for any batch
+    // (the curve walker over max_curves workgroups).
     struct Slot {
         uint8_t* host = nullptr;    // pinned header + curve table
         uint8_t* dev = nullptr;     // its device copy
@@ -742,13 +789,16 @@ namespace noalloc {
 constexpr int64_t kMaxSamples = UMI_NOALLOC_MAX_SAMPLES;
 constexpr int64_t kMaxCurves = UMI_NOALLOC_MAX_CURVES;
 constexpr int64_t kMaxTiles = UMI_NOALLOC_MAX_TILES;
+// every curve adds at most one partial chunk
+constexpr int64_t kMaxChunks = kMaxSamples / kPrepChunk + kMaxCurves;
 constexpr size_t kAlign = 256;
 constexpr size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // byte offsets inside the scratch array
 constexpr size_t kBlockOff = 0;  // BatchHeader + curve table
 constexpr size_t kCounterOff = round_up(sizeof(BatchHeader) + kMaxCurves * sizeof(CurveDesc));
-constexpr size_t kTilesOff = kCounterOff + kAlign;
+constexpr size_t kRecsOff = kCounterOff + kAlign;
+constexpr size_t kTilesOff = round_up(kRecsOff + kMaxChunks * sizeof(ChunkRec));
 constexpr size_t kSegidOff = round_up(kTilesOff + kMaxTiles * sizeof(int2));
 constexpr size_t kScratchBytes = kSegidOff + kMaxSamples * sizeof(int32_t);
 static_assert(kScratchBytes == UMI_NOALLOC_SCRATCH_BYTES, "scratch size in umi.h");
@@ -842,7 +892,8 @@ umi_status detrend_batch(const float* flux, const double* time, const int64_t* l
         return fail(UMI_ERR_UNSUPPORTED,
                     "umi_detrend_batch_noalloc: the batch needs more than UMI_NOALLOC_MAX_TILES "
                     "tiles (very wide windows cut curves into small tiles)");
-    write_block(g_block, g_curves, v.ncurves, v.ntiles, iters, o, time);
+    if (v.nchunks > kMaxChunks) return fail(UMI_ERR_UNSUPPORTED, "chunk count above its bound");
+    write_block(g_block, g_curves, v.ncurves, v.ntiles, v.nchunks, iters, o, time);
     // from pageable host memory: the source is free again once the call returns
     if ((e = hipMemcpyAsync(base + kBlockOff, g_block, block_bytes(v.ncurves),
                             hipMemcpyHostToDevice, stream)) != hipSuccess)
@@ -852,12 +903,14 @@ umi_status detrend_batch(const float* flux, const double* time, const int64_t* l
     b.cap_segid = kMaxSamples;
     b.tiles = reinterpret_cast<int2*>(base + kTilesOff);
     b.cap_tiles = kMaxTiles;
-    b.counter = reinterpret_cast<uint32_t*>(base + kCounterOff);
-    b.cap_counter = 1;
+    b.ctr = reinterpret_cast<Counters*>(base + kCounterOff);  // zero from the module load
+    b.cap_ctr = 1;
+    b.recs = reinterpret_cast<ChunkRec*>(base + kRecsOff);
+    b.cap_recs = kMaxChunks;
     const int grid = (int)std::min<int64_t>(v.ntiles, (int64_t)v.gpc * n_cu);
     e = enqueue_kernels(flux, time, trend, median, base + kBlockOff, b, opt.mode, g_curves,
-                        g_curve_tiles, (int)v.ncurves, grid, (hipEvent_t)opt.main_start,
-                        (hipEvent_t)opt.main_stop, stream);
+                        g_curve_tiles, (int)v.ncurves, prep_launch_for(v.ncurves, v.nchunks, n_cu),
+                        grid, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -980,18 +1033,23 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
                                        std::max(sized_tiles, 2 * n_cu)) + max_curves;
     if (max_tiles > (int64_t)INT32_MAX)
         return umi::fail(UMI_ERR_UNSUPPORTED, "plan capacity needs too many tiles");
+    // every curve adds at most one partial chunk
+    const int64_t max_chunks = capacity / umi::kPrepChunk + max_curves;
+    if (max_chunks > (int64_t)INT32_MAX)
+        return umi::fail(UMI_ERR_UNSUPPORTED, "plan capacity needs too many pre-pass chunks");
     umi_plan* p = new umi_plan();
     p->device = device;
     p->stream = static_cast<hipStream_t>(stream);
     p->capacity = capacity;
     p->max_curves = max_curves;
     p->max_tiles = max_tiles;
+    p->max_chunks = max_chunks;
     p->max_W = max_W;
     p->flux = flux;
     p->time = time;
     p->trend = trend;
     p->median = median;
-    hipError_t e = p->buf.reserve(capacity, max_tiles, /*exact=*/true);
+    hipError_t e = p->buf.reserve(capacity, max_tiles, max_chunks, p->stream, /*exact=*/true);
     const size_t bytes = umi::block_bytes(max_curves);
     for (auto& s : p->slot) {
         if (e == hipSuccess)
@@ -1000,6 +1058,8 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e == hipSuccess) std::memset(s.host, 0, bytes);
     }
+    // the workspace's zero fill is done before anything is captured
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         plan_free(p);
         delete p;
@@ -1042,6 +1102,8 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
         return st;
     if (pk.ntiles > p->max_tiles)
         return umi::fail(UMI_ERR_UNSUPPORTED, "batch needs more tiles than the plan holds");
+    if (pk.nchunks > p->max_chunks)
+        return umi::fail(UMI_ERR_UNSUPPORTED, "batch needs more chunks than the plan holds");
 
     std::lock_guard<std::mutex> lk(p->mu);
     umi_plan::Slot& s = p->slot[p->next];
@@ -1051,13 +1113,16 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
             return umi::fail_hip(e, "hipEventSynchronize");
         s.pending = false;
     }
-    umi::write_block(s.host, pk.curves.data(), (int64_t)pk.curves.size(), pk.ntiles, iters, o,
-                     p->time);
-    // few curves: the wide pre-pass over kPrepWideCurves workgroups instead
-    // of one narrow workgroup per possible curve
-    const int kind = (int64_t)pk.curves.size() <= umi::kPrepWideCurves ? 0 : 1;
+    umi::write_block(s.host, pk.curves.data(), (int64_t)pk.curves.size(), pk.ntiles, pk.nchunks,
+                     iters, o, p->time);
+    // small batches: the chunked pre-pass over kPrepSmallChunks workgroups
+    // (each curve has a chunk, so the table holds at most that many curves);
+    // larger ones: the curve walker, one workgroup per possible curve
+    const int kind = pk.nchunks <= umi::kPrepSmallChunks ? 0 : 1;
     const int64_t cap_curves =
-        kind == 0 ? std::min<int64_t>(p->max_curves, umi::kPrepWideCurves) : p->max_curves;
+        kind == 0 ? std::min<int64_t>(p->max_curves, umi::kPrepSmallChunks) : p->max_curves;
+    const umi::PrepLaunch prep = kind == 0 ? umi::PrepLaunch{false, umi::kPrepSmallChunks}
+                                           : umi::PrepLaunch{true, (int)p->max_curves};
     if (!s.exec[kind]) {
         // capture once per slot and kind: copy of the staged block, pre-pass
         // over cap_curves (blocks beyond the batch exit), persistent estimate
@@ -1068,7 +1133,7 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
         if (ce == hipSuccess)
             ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
                                       UMI_MODE_PERSISTENT, nullptr, nullptr, (int)cap_curves,
-                                      p->main_grid, nullptr, nullptr, p->stream);
+                                      prep, p->main_grid, nullptr, nullptr, p->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->stream, &g);
         if (ce != hipSuccess || e != hipSuccess) {

@@ -23,10 +23,14 @@ __host__ __device__ constexpr int split_lanes(int tile)
     return tile > kSplitMaxTile ? 1 : (tile > kMainThreads / 4 ? 2 : (tile > kMainThreads / 8 ? 4 : 8));
 }
 constexpr int kPrepThreads = 256;            // threads per pre-pass workgroup
-constexpr int kPrepWideThreads = 1024;       // ... when a launch covers few curves
-constexpr int kPrepWideCurves = 64;          // "few": at most this many
-constexpr int kPrepItems = 4;                // samples per pre-pass thread per chunk
-constexpr int kPrepWideItems = 8;            // ... in the 1024-thread workgroups
+constexpr int kPrepItems = 8;                // samples per thread per chunk (chunked pre-pass)
+constexpr int kPrepChunk = kPrepThreads * kPrepItems;  // samples per pre-pass chunk
+constexpr int kPrepWalkItems = 4;            // samples per thread per step (curve walker)
+constexpr int kPrepGroupsPerCU = 8;          // chunked pre-pass workgroups per CU
+constexpr int kPrepSmallChunks = 256;        // plan steps of at most this many chunks take
+                                             // a chunked pre-pass of this many workgroups
+constexpr int kPrepWalkMinCurves = 128;      // batches of this many curves or more take the
+                                             // one-workgroup-per-curve walker
 constexpr float kScaleConst = 0.6745f;       // Section 2.2, after Eq. 1
 constexpr double kGapDays = 0.5;             // segment break threshold (days)
 
@@ -38,10 +42,12 @@ struct BatchHeader {
     int32_t n_tiles;    // tiles over all curves
     int32_t iters;      // Phase 3 iterations
     int32_t scale;      // umi_scale: Phase 2 estimator
+    int32_t n_chunks;   // pre-pass chunks over all curves
+    int32_t reserved;
     float* detrended;   // flux / trend output (curve offsets as for trend), or null
     const double* time; // the batch's times (read by the time-window scans), or null
 };
-static_assert(sizeof(BatchHeader) == 32, "BatchHeader layout");
+static_assert(sizeof(BatchHeader) == 40, "BatchHeader layout");
 
 // One curve of a packed batch, in the (cost-sorted) order tiles are issued.
 struct CurveDesc {
@@ -53,8 +59,51 @@ struct CurveDesc {
     float alpha;        // asymmetry factor (Eq. 2) of this curve
     float c;            // bisquare tuning constant of this curve
     double window_days; // > 0: time window of this length (W still bounds it)
+    int32_t chunk_base; // index of this curve's first pre-pass chunk
+    int32_t reserved;
 };
-static_assert(sizeof(CurveDesc) == 40, "CurveDesc layout");
+static_assert(sizeof(CurveDesc) == 48, "CurveDesc layout");
+
+// Segmentation summary of a run of consecutive samples of one curve, or the
+// state after a curve's first samples (a prefix), as the pre-pass scan
+// carries it from chunk to chunk.
+struct SegState {
+    int32_t cnt;        // valid samples
+    int32_t fv;         // first valid sample (curve-local), -1 if none
+    int32_t lv;         // last valid sample, -1 if none
+    int32_t ls;         // latest segment start, -1 if none; in a run that is
+                        // not a prefix only starts after fv count (fv's own
+                        // status depends on what precedes the run)
+    int32_t lsb;        // valid samples of the run (or prefix) before ls
+    int32_t reserved;
+    double ft;          // time of fv
+    double lt;          // time of lv
+};
+static_assert(sizeof(SegState) == 40, "SegState layout");
+
+// One pre-pass chunk's published scan state: its own summary (`agg`), then
+// the state after the curve's samples up to its end (`inc`).  Each holds the
+// nine 32-bit words of a SegState (cnt, fv, lv, ls, lsb, then the low and
+// high halves of ft and lt), each stored in the low half of a 64-bit word
+// whose high half is the launch's stamp: a reader takes a state once all nine
+// words carry its launch's stamp, so no word needs ordering against another.
+constexpr int kSegWords = 9;
+struct ChunkRec {
+    uint64_t agg[kSegWords];
+    uint64_t inc[kSegWords];
+};
+static_assert(sizeof(ChunkRec) == 144, "ChunkRec layout");
+
+// Device counters of a workspace (zeroed when it is allocated).
+struct Counters {
+    uint32_t queue;     // estimate-kernel tile queue (cleared by the pre-pass)
+    uint32_t tickets;   // pre-pass chunk tickets (reset by its last workgroup)
+    uint32_t done;      // pre-pass workgroups finished (reset likewise)
+    uint32_t reserved;
+    uint64_t epoch;     // pre-pass launches completed; stamps use epoch + 1
+    uint64_t reserved2;
+};
+static_assert(sizeof(Counters) == 32, "Counters layout");
 
 // Per-sample segment word written by the pre-pass at segid[curve.off + i]:
 //   -1       sample i is invalid;

@@ -2,11 +2,16 @@
 //
 // Two kernels run per batch, both on the caller's stream:
 //
-//   umi_prepass_kernel  one workgroup per curve.  Validity and segmentation
-//                       (gap handling, minimum segment length W/3 of
-//                       Section 4.4): a chunked block scan writes a segment id
-//                       per sample and one record per segment, and lays out the
-//                       curve's tile list for the main kernel.
+//   pre-pass            validity and segmentation (gap handling, minimum
+//                       segment length W/3 of Section 4.4): block scans write
+//                       a segment word per sample and one record per segment,
+//                       and lay out the tile list for the main kernel.  Two
+//                       forms: umi_prepass_walk_kernel walks each curve with
+//                       one workgroup (batches of many curves);
+//                       umi_prepass_chunk_kernel cuts curves into chunks of
+//                       2,048 samples taken in ticket order, each joined to
+//                       the curve before it by a decoupled look-back (few
+//                       curves, so that a lone curve is spread over the chip).
 //
 //   umi_main_kernel     tiles of consecutive output positions.  A workgroup
 //                       stages a tile plus its W-1 halo from HBM once, keeps the
@@ -100,8 +105,9 @@ __device__ __forceinline__ void wave_incl_latest_sum(int& idx, T& val, int& cnt)
 // ---------------------------------------------------------------------------
 // Pre-pass: segments and tiles.
 //
-// One workgroup walks one curve in chunks of NT * K samples (K consecutive
-// samples per thread).  It writes one int32 per sample:
+// Curves are cut into chunks of kPrepChunk samples (kPrepItems consecutive
+// samples per thread); workgroups take chunks in ticket order from a device
+// counter and scan each in one pass.  The pre-pass writes one int32 per sample:
 //   -1                    the sample is invalid (non-finite flux or time);
 //   x >= 0                a valid sample whose segment starts at the valid
 //                         sample x (curve-local index), x < this sample;
@@ -111,16 +117,437 @@ __device__ __forceinline__ void wave_incl_latest_sum(int& idx, T& val, int& cnt)
 // A new segment starts at a valid sample whose predecessor among valid
 // samples is more than kGapDays earlier (strictly), and at the first valid
 // sample.  The slot of a segment's first sample is written once, by whoever
-// sees the segment end (the thread holding the next start, or thread 0 at the
-// end of the curve), so no slot has two writers.  The scans per chunk: the
-// latest valid sample (index, time) with the valid count, then the latest
-// segment start (index, valid count before it); chunk carries make them
-// curve-wide.  Two barriers per chunk: each LDS array is written in one phase
-// and read in the next, and a phase's writes follow the barrier that ends
-// every wave's reads of the same array in the chunk before.
+// sees the segment end (the thread holding the next start, or the workgroup of
+// the curve's last chunk), so no slot has two writers.
+//
+// A chunk's output depends on the curve before it only through a small state
+// (SegState: valid count, last valid sample and its time, latest segment
+// start).  Each workgroup first scans its chunk alone and publishes the
+// chunk's summary; it then finds the state before the chunk by looking back
+// over its predecessors' records -- 64 at a time, one per lane -- combining
+// summaries until it meets one whose state is final (a decoupled look-back),
+// publishes its own final state, and writes its segment words.  Tickets are
+// handed out in order, so every chunk a workgroup waits for belongs to a
+// workgroup that has already started, and every workgroup publishes its
+// summary before it waits for anything: the waits always end.
+
+// The state after run `a` followed by run `b`.  `a_prefix`: `a` starts at the
+// curve's first sample, so after an empty `a` the first valid sample of `b`
+// starts a segment.  The gap test is the expression the per-sample scan uses.
+__device__ __forceinline__ SegState seg_combine(const SegState& a, const SegState& b, bool a_prefix,
+                                                bool has_time)
+{
+    if (b.cnt == 0) return a;
+    SegState r = b;
+    if (a.cnt == 0) {
+        if (a_prefix && b.ls < 0) {
+            r.ls = b.fv;
+            r.lsb = 0;
+        }
+        return r;
+    }
+    r.cnt = a.cnt + b.cnt;
+    r.fv = a.fv;
+    r.ft = a.ft;
+    if (b.ls >= 0) {
+        r.lsb = a.cnt + b.lsb;
+    } else if (has_time && (b.ft - a.lt) > kGapDays) {
+        r.ls = b.fv;
+        r.lsb = a.cnt;
+    } else {
+        r.ls = a.ls;
+        r.lsb = a.lsb;
+    }
+    return r;
+}
+
+__device__ __forceinline__ SegState seg_empty()
+{
+    SegState e;
+    e.cnt = 0;
+    e.fv = e.lv = e.ls = -1;
+    e.lsb = 0;
+    e.reserved = 0;
+    e.ft = e.lt = 0.0;
+    return e;
+}
+
+constexpr int kSpinLimit = 1 << 20;  // polls of one record before giving up (never reached)
+
+// Word i of a SegState (see ChunkRec) and the reverse.
+__device__ __forceinline__ uint32_t seg_word(const SegState& s, int i)
+{
+    const uint64_t ft = __double_as_longlong(s.ft), lt = __double_as_longlong(s.lt);
+    switch (i) {
+    case 0: return (uint32_t)s.cnt;
+    case 1: return (uint32_t)s.fv;
+    case 2: return (uint32_t)s.lv;
+    case 3: return (uint32_t)s.ls;
+    case 4: return (uint32_t)s.lsb;
+    case 5: return (uint32_t)ft;
+    case 6: return (uint32_t)(ft >> 32);
+    case 7: return (uint32_t)lt;
+    default: return (uint32_t)(lt >> 32);
+    }
+}
+
+__device__ __forceinline__ SegState seg_from_words(const uint32_t (&v)[kSegWords])
+{
+    SegState s;
+    s.cnt = (int32_t)v[0];
+    s.fv = (int32_t)v[1];
+    s.lv = (int32_t)v[2];
+    s.ls = (int32_t)v[3];
+    s.lsb = (int32_t)v[4];
+    s.reserved = 0;
+    s.ft = __longlong_as_double((long long)(((uint64_t)v[6] << 32) | v[5]));
+    s.lt = __longlong_as_double((long long)(((uint64_t)v[8] << 32) | v[7]));
+    return s;
+}
+
+// Publish a state: lane i < kSegWords of the calling wave stores word i with
+// the stamp (relaxed device-scope atomics: no cache flush, no ordering).
+__device__ __forceinline__ void seg_publish(uint64_t* words, const SegState& s, uint32_t stamp)
+{
+    const int lane = __lane_id();
+    if (lane < kSegWords)
+        __hip_atomic_store(&words[lane], ((uint64_t)stamp << 32) | seg_word(s, lane),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Read a state if every word carries `stamp`.
+__device__ __forceinline__ bool seg_read(const uint64_t* words, uint32_t stamp, SegState& out)
+{
+    uint32_t v[kSegWords];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < kSegWords; ++i) {
+        const uint64_t w = __hip_atomic_load(&words[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = ok && (uint32_t)(w >> 32) == stamp;
+        v[i] = (uint32_t)w;
+    }
+    if (ok) out = seg_from_words(v);
+    return ok;
+}
+
+// The state before chunk g of a curve whose first chunk is g0 (g > g0), from
+// the predecessors' records; run by one whole wave.  Lane l examines chunk
+// g - 1 - l - 64 k in round k; the nearest chunk with a final state ends the
+// walk, and the summaries of the chunks after it are combined in order.  The
+// result is returned in every lane.
+__device__ SegState lookback(const ChunkRec* __restrict__ recs, int g, int g0, uint32_t stamp,
+                             bool has_time, SegState* sh /* [64] */)
+{
+    const int lane = __lane_id();
+    SegState acc = seg_empty();  // the chunks after the current window, in order
+    for (int hi = g - 1;; hi -= 64) {
+        const int j = hi - lane;
+        int status = 2;  // before the curve's first chunk: the empty prefix
+        SegState st = seg_empty();
+        if (j >= g0) {
+            status = 0;
+            for (int polls = 0; polls < kSpinLimit && status == 0; ++polls) {
+                if (seg_read(recs[j].inc, stamp, st))
+                    status = 2;
+                else if (seg_read(recs[j].agg, stamp, st))
+                    status = 1;
+                else
+                    __builtin_amdgcn_s_sleep(1);
+            }
+            if (status == 0) status = 2;  // a timeout reads as final
+        }
+        sh[lane] = st;
+        const uint64_t fin = __ballot(status == 2);
+        const int k = fin ? __builtin_ctzll(fin) : 64;  // nearest final state in this window
+        // every lane's state is in LDS before lane 0 reads them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            for (int i = 0; i < k; ++i) acc = seg_combine(sh[i], acc, false, has_time);
+            if (k < 64) acc = seg_combine(sh[k], acc, true, has_time);
+            sh[0] = acc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        acc = sh[0];  // every lane
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (k < 64) break;
+    }
+    return acc;
+}
 
 template <int NT, int K>
-__global__ __launch_bounds__(NT) void umi_prepass_kernel(
+__global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
+    const float* __restrict__ flux, const double* __restrict__ time,
+    const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_one,
+    int32_t* __restrict__ segid, int2* __restrict__ tiles, Counters* __restrict__ ctr,
+    ChunkRec* __restrict__ recs, int clear_queue)
+{
+    constexpr int NW = NT / 64;
+    constexpr int kChunk = NT * K;
+    __shared__ int sh_vi[NW];      // per wave: latest valid index
+    __shared__ double sh_vt[NW];   //           its time
+    __shared__ int sh_vc[NW];      //           valid count
+    __shared__ int sh_sx[NW];      // per wave: latest segment start
+    __shared__ int sh_sz[NW];      //           valid samples before it
+    __shared__ int sh_fv;          // the chunk's first valid sample
+    __shared__ double sh_ft;       //   its time
+    __shared__ int sh_ticket, sh_curve;
+    __shared__ SegState sh_carry;  // the curve's state before the chunk
+    __shared__ SegState sh_lb[64]; // look-back window
+
+    const int tid = (int)threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = __lane_id();
+    if (clear_queue && blockIdx.x == 0 && tid == 0) ctr->queue = 0u;
+    const uint64_t epoch_word = ctr->epoch;
+    const uint32_t stamp = (uint32_t)(epoch_word + 1);  // this launch's record stamp
+    // one curve (per-curve launches) or the whole batch
+    const int n_chunks = curve_one >= 0
+                             ? (curves[curve_one].len + kChunk - 1) / kChunk
+                             : hdr->n_chunks;
+    const int n_curves = hdr->n_curves;
+
+    for (;;) {
+        if (tid == 0) sh_ticket = (int)atomicAdd(&ctr->tickets, 1u);
+        __syncthreads();
+        const int g = sh_ticket;
+        if (g >= n_chunks) break;
+        // the chunk's curve: the last table entry whose first chunk is <= g
+        // (a 64-way search by wave 0; chunk_base increases along the table)
+        if (curve_one >= 0) {
+            if (tid == 0) sh_curve = curve_one;
+        } else if (w == 0) {
+            int lo = 0, hi = n_curves;
+            while (hi - lo > 1) {
+                const int step = (hi - lo + 63) / 64;
+                const int idx = lo + lane * step;
+                const bool le = idx < hi && curves[idx].chunk_base <= g;
+                const uint64_t m = __ballot(le);
+                const int last = 63 - __builtin_clzll(m);  // lane 0 always qualifies
+                lo = lo + last * step;
+                hi = min(lo + step, hi);
+            }
+            if (lane == 0) sh_curve = lo;
+        }
+        __syncthreads();
+        const int cidx = sh_curve;
+        const CurveDesc cd = curves[cidx];
+        const int g0 = curve_one >= 0 ? 0 : cd.chunk_base;  // the curve's first chunk
+        const int lo = (g - g0) * kChunk;
+        const int hi = min(lo + kChunk, cd.len);
+        const float* f = flux + cd.off;
+        const double* tm = time ? time + cd.off : nullptr;
+        const bool has_time = tm != nullptr;
+        int32_t* sid = segid + cd.off;
+
+        // the tiles that start in this chunk
+        for (int t = (lo + cd.tile - 1) / cd.tile + tid; t * cd.tile < hi; t += NT)
+            tiles[cd.tile_base + t] = make_int2(cidx, t * cd.tile);
+
+        float fv[K];
+        double tv[K];
+        const int e0 = lo + tid * K;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int e = e0 + q;
+            fv[q] = e < hi ? f[e] : __builtin_nanf("");
+            tv[q] = (has_time && e < hi) ? tm[e] : 0.0;
+        }
+        uint32_t vmask = 0;  // bit q: item q is valid
+        int vi = -1, vc = 0, fi = -1;
+        double vt = 0.0, ft = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const bool ok = e0 + q < hi && isfinite(fv[q]) && (!has_time || isfinite(tv[q]));
+            vmask |= (ok ? 1u : 0u) << q;
+            if (ok) {
+                if (fi < 0) {
+                    fi = e0 + q;
+                    ft = tv[q];
+                }
+                vi = e0 + q;
+                vt = tv[q];
+                ++vc;
+            }
+        }
+
+        // phase 1 (chunk alone): latest valid sample and valid count before
+        // this thread's items, the chunk's first and last valid samples
+        const int own_vc = vc;
+        wave_incl_latest_sum(vi, vt, vc);
+        if (lane == 63) {
+            sh_vi[w] = vi;
+            sh_vt[w] = vt;
+            sh_vc[w] = vc;
+        }
+        int ex_i = __shfl_up(vi, 1, 64);
+        double ex_t = __shfl_up(vt, 1, 64);
+        int before = vc - own_vc;  // valid samples earlier in this wave
+        if (lane == 0) ex_i = -1;
+        __syncthreads();
+        int tot = 0, blk_i = -1;
+        double blk_t = 0.0;
+        for (int i = 0; i < NW; ++i) {
+            if (i == w && ex_i < 0) {  // nothing valid earlier in this wave
+                ex_i = blk_i;
+                ex_t = blk_t;
+            }
+            if (i < w) before += sh_vc[i];
+            tot += sh_vc[i];
+            if (sh_vi[i] >= 0) {
+                blk_i = sh_vi[i];
+                blk_t = sh_vt[i];
+            }
+        }
+        if (before == 0 && own_vc > 0) {  // the thread holding the chunk's first valid sample
+            sh_fv = fi;
+            sh_ft = ft;
+        }
+
+        // phase 2 (chunk alone): segment starts that follow a valid sample of
+        // the chunk, then the latest such start before this thread's items
+        int sx = -1, sz = 0;
+        {
+            int pi = ex_i;
+            double pt = ex_t;
+            int v = before;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                if ((vmask >> q) & 1u) {
+                    if (pi >= 0 && has_time && (tv[q] - pt) > kGapDays) {
+                        sx = e0 + q;
+                        sz = v;
+                    }
+                    pi = e0 + q;
+                    pt = tv[q];
+                    ++v;
+                }
+            }
+        }
+        wave_incl_latest(sx, sz);
+        if (lane == 63) {
+            sh_sx[w] = sx;
+            sh_sz[w] = sz;
+        }
+        int px = __shfl_up(sx, 1, 64);
+        int pz = __shfl_up(sz, 1, 64);
+        if (lane == 0) px = -1;
+        __syncthreads();
+        int bx = -1, bz = 0;
+        for (int i = 0; i < NW; ++i) {
+            if (i == w && px < 0) {
+                px = bx;
+                pz = bz;
+            }
+            if (sh_sx[i] >= 0) {
+                bx = sh_sx[i];
+                bz = sh_sz[i];
+            }
+        }
+
+        // publish the chunk's summary, find the state before it, publish the
+        // state after it (wave 0)
+        if (w == 0) {
+            SegState agg = seg_empty();
+            if (tot > 0) {
+                agg.cnt = tot;
+                agg.fv = sh_fv;
+                agg.ft = sh_ft;
+                agg.lv = blk_i;
+                agg.lt = blk_t;
+                agg.ls = bx;
+                agg.lsb = bz;
+            }
+            SegState carry = seg_empty();
+            if (g > g0) {
+                seg_publish(recs[g].agg, agg, stamp);
+                carry = lookback(recs, g, g0, stamp, has_time, sh_lb);
+            }
+            const SegState inc = seg_combine(carry, agg, true, has_time);  // every lane
+            seg_publish(recs[g].inc, inc, stamp);
+            if (lane == 0) {
+                sh_carry = carry;
+                // the curve's last segment ends with its last chunk
+                if (hi == cd.len && inc.ls >= 0) sid[inc.ls] = -2 - (inc.cnt - inc.lsb);
+            }
+        }
+        __syncthreads();
+        const SegState cy = sh_carry;
+        const int fv0 = sh_fv;      // the chunk's first valid sample (when tot > 0)
+        const double ft0 = sh_ft;
+
+        // writes: segment of each item; a start closes the segment before it.
+        // The state entering this thread's items comes from the chunk scan
+        // where the chunk holds something before them, else from the carry;
+        // it is formed with selects only.
+        {
+            const bool local_pred = ex_i >= 0;
+            int pi = local_pred ? ex_i : cy.lv;
+            double pt = local_pred ? ex_t : cy.lt;
+            int v = cy.cnt + before;
+            // the chunk's first valid sample starts a segment when nothing
+            // valid precedes it in the curve or the gap to it is too long
+            const bool first_starts =
+                tot > 0 && (cy.cnt == 0 || (has_time && (ft0 - cy.lt) > kGapDays));
+            const bool local_start = px >= 0;
+            const bool use_fv = !local_start && first_starts && fv0 < e0;
+            pz = local_start ? pz + cy.cnt : (use_fv ? cy.cnt : cy.lsb);
+            px = local_start ? px : (use_fv ? fv0 : cy.ls);
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const int e = e0 + q;
+                if (e < hi) {
+                    if ((vmask >> q) & 1u) {
+                        if (pi < 0 || (has_time && (tv[q] - pt) > kGapDays)) {
+                            if (px >= 0) sid[px] = -2 - (v - pz);
+                            px = e;
+                            pz = v;
+                        } else {
+                            sid[e] = px;
+                        }
+                        pi = e;
+                        pt = tv[q];
+                        ++v;
+                    } else {
+                        sid[e] = -1;
+                    }
+                }
+            }
+        }
+        __syncthreads();  // LDS of this chunk is reused by the next
+    }
+
+    // the last workgroup to finish resets the tickets for the next launch.
+    // Every workgroup's final ticket increment has returned its value before
+    // the workgroup counts itself done, so once `done` shows all of them no
+    // increment is outstanding.
+    if (tid == 0) {
+        const uint32_t old =
+            __hip_atomic_fetch_add(&ctr->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            __hip_atomic_store(&ctr->tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr->epoch, epoch_word + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// The same segment words and tiles from one workgroup per curve, which walks
+// the curve's chunks of NT * K samples in order and carries the scan state in
+// registers (the next chunk's loads are issued before the current chunk's
+// scans).  No tickets, records or look-back: batches of many curves fill the
+// chip this way, and every chunk costs one pass.  Two barriers per chunk:
+// each LDS array is written in one phase and read in the next, and a phase's
+// writes follow the barrier that ends every wave's reads of the same array in
+// the chunk before.
+template <int NT, int K>
+__global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
     const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_first,
     int32_t* __restrict__ segid, int2* __restrict__ tiles, uint32_t* __restrict__ counter)
@@ -1141,21 +1568,20 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 // Host-side launch wrappers (the host library calls only these).
 
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
-                          int2* tiles, uint32_t* counter, hipStream_t stream)
+                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
+                          int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
+                          hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    // A launch over few curves walks each curve with a 1024-thread workgroup
-    // of 8 samples per thread (an eighth as many chunks in sequence); many
-    // curves fill the chip with 256-thread workgroups, one per curve.
-    if (grid <= kPrepWideCurves)
-        hipLaunchKernelGGL((umi_prepass_kernel<kPrepWideThreads, kPrepWideItems>), dim3(grid),
-                           dim3(kPrepWideThreads), 0, stream, flux, time, hdr, curves,
-                           curve_first, segid, tiles, counter);
+    if (walk)  // one workgroup per curve, from curve_one (or the first) on
+        hipLaunchKernelGGL((umi_prepass_walk_kernel<kPrepThreads, kPrepWalkItems>), dim3(grid),
+                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves,
+                           curve_one < 0 ? 0 : curve_one, segid, tiles,
+                           clear_queue ? &ctr->queue : nullptr);
     else
-        hipLaunchKernelGGL((umi_prepass_kernel<kPrepThreads, kPrepItems>), dim3(grid),
-                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves, curve_first,
-                           segid, tiles, counter);
+        hipLaunchKernelGGL((umi_prepass_chunk_kernel<kPrepThreads, kPrepItems>), dim3(grid),
+                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves, curve_one,
+                           segid, tiles, ctr, recs, clear_queue ? 1 : 0);
     return hipGetLastError();
 }
 

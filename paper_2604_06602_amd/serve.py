@@ -42,7 +42,8 @@ import numpy as np
 
 # Device bytes held per resident sample: flux f32, time f64, trend f32, and
 # the plan workspace: one i32 segment word per sample plus the tile list
-# (8 bytes per tile of at least 512 samples, rounded up to 1 byte per sample).
+# (8 bytes per tile of at least 512 samples) and the pre-pass chunk records
+# (144 bytes per 2,048 samples), together rounded up to 1 byte per sample.
 BYTES_PER_SAMPLE = 4 + 8 + 4 + 4 + 1
 
 

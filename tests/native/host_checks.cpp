@@ -35,35 +35,67 @@ long g_prepass = 0, g_main = 0;
 
 namespace umi {
 
-// The pre-pass: every curve of the grid reads its flux and time and writes
-// a segment word per sample and its tile records (what the kernel writes).
+// The pre-pass: chunk g of the launch maps to its curve as in the kernel (the
+// last table entry whose first chunk is <= g, or the launch's one curve);
+// every chunk reads its flux and time, writes its segment words, its chunk
+// record and the tiles that start in it (what the kernel writes), and the
+// counters come back to zero with the launch count advanced.
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_first, int grid, int32_t* segid,
-                          int2* tiles, uint32_t* counter, hipStream_t)
+                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
+                          int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
+                          hipStream_t)
 {
     ++g_prepass;
-    if (counter) *counter = 0u;
-    CHECK(hdr->n_curves >= 0 && hdr->n_tiles >= 0);
-    for (int b = 0; b < grid; ++b) {
-        const int ci = curve_first + b;
-        if (ci >= hdr->n_curves) break;
+    CHECK(grid >= 1);
+    if (walk && curve_one < 0) CHECK(grid >= hdr->n_curves);  // a workgroup per curve
+    if (walk && curve_one >= 0) CHECK(grid == 1);
+    CHECK(hdr->n_curves >= 0 && hdr->n_tiles >= 0 && hdr->n_chunks >= 0);
+    CHECK(ctr->tickets == 0u && ctr->done == 0u);
+    if (clear_queue) ctr->queue = 0u;
+    if (curve_one < 0) {
+        int64_t next = 0;
+        for (int c = 0; c < hdr->n_curves; ++c) {
+            CHECK(curves[c].chunk_base == next);
+            next += (curves[c].len + kPrepChunk - 1) / kPrepChunk;
+        }
+        CHECK(next == hdr->n_chunks);
+    } else {
+        CHECK(curve_one < hdr->n_curves);
+    }
+    const int n_chunks = curve_one >= 0 ? (curves[curve_one].len + kPrepChunk - 1) / kPrepChunk
+                                        : hdr->n_chunks;
+    for (int g = 0; g < n_chunks; ++g) {
+        int ci = curve_one;
+        if (ci < 0) {
+            ci = 0;
+            while (ci + 1 < hdr->n_curves && curves[ci + 1].chunk_base <= g) ++ci;
+        }
         const CurveDesc& cd = curves[ci];
         CHECK(cd.len > 0 && cd.W >= 1 && (cd.W & 1) == 1 && cd.tile >= 1);
         CHECK(cd.tile <= kMaxTile && cd.tile + cd.W - 1 <= kStageMax);
         const int nt = (cd.len + cd.tile - 1) / cd.tile;
         CHECK(cd.tile_base >= 0 && cd.tile_base + nt <= hdr->n_tiles);
-        for (int t = 0; t < nt; ++t) tiles[cd.tile_base + t] = make_int2(ci, t * cd.tile);
+        const int g0 = curve_one >= 0 ? 0 : cd.chunk_base;
+        const int lo = (g - g0) * kPrepChunk, hi = std::min(lo + kPrepChunk, cd.len);
+        CHECK(lo >= 0 && lo < cd.len);
+        for (int i = 0; i < kSegWords; ++i) {
+            recs[g].agg[i] = (ctr->epoch + 1) << 32 | (uint32_t)(hi - lo);
+            recs[g].inc[i] = (ctr->epoch + 1) << 32 | (uint32_t)hi;
+        }
+        for (int t = (lo + cd.tile - 1) / cd.tile; t * cd.tile < hi; ++t)
+            tiles[cd.tile_base + t] = make_int2(ci, t * cd.tile);
         volatile float fs = 0.0f;
         volatile double ts = 0.0;
-        for (int i = 0; i < cd.len; ++i) {
+        for (int i = lo; i < hi; ++i) {
             fs = fs + flux[cd.off + i];
             if (time) ts = ts + time[cd.off + i];
             segid[cd.off + i] = -1;
         }
         if (hdr->detrended)
-            for (int i = 0; i < cd.len; ++i) hdr->detrended[cd.off + i] = 0.0f;
+            for (int i = lo; i < hi; ++i) hdr->detrended[cd.off + i] = 0.0f;
         if (hdr->time) CHECK(hdr->time == time);
     }
+    ctr->epoch += 1;
     return hipSuccess;
 }
 
@@ -239,6 +271,42 @@ void check_plans()
     }
 }
 
+// The allocation-free call: random batches within its limits run through the
+// same checkers on the static workspace; batches beyond them are refused
+// before any launch, and no call allocates device memory.
+void check_noalloc()
+{
+    for (int round = 0; round < std::max(2, g_rounds / 10); ++round) {
+        const int64_t n = uni(1, 30);
+        std::vector<int64_t> len((size_t)n);
+        std::vector<int32_t> W((size_t)n);
+        int64_t total = 0;
+        for (int64_t b = 0; b < n; ++b) {
+            len[b] = uni(0, 70000);
+            W[b] = odd_w(uni(0, 3) == 0 ? 2047 : 721);
+            total += len[b];
+        }
+        DevArrays a(std::max<int64_t>(total, 1));
+        umi_launch lo = {uni(0, 3) == 0 ? UMI_MODE_PER_CURVE : UMI_MODE_PERSISTENT, 0, 0, 0,
+                         nullptr, nullptr};
+        const long before = g_prepass;
+        const long mallocs = fake_hip::device_mallocs();
+        const umi_status st = umi_detrend_batch_noalloc(a.flux, uni(0, 1) ? a.time : nullptr,
+                                                        len.data(), n, W.data(), 2.0f, 5.0f, 5,
+                                                        a.trend, a.median, &lo, nullptr);
+        CHECK(st == UMI_OK || st == UMI_ERR_UNSUPPORTED);  // tiles of W near 2047
+        if (st == UMI_OK && total > 0) CHECK(g_prepass > before);
+        CHECK(fake_hip::device_mallocs() == mallocs);
+    }
+    std::vector<int64_t> big = {UMI_NOALLOC_MAX_SAMPLES, 1};
+    std::vector<int32_t> w2 = {25, 25};
+    const long before = g_prepass;
+    CHECK(umi_detrend_batch_noalloc(reinterpret_cast<float*>(16), nullptr, big.data(), 2,
+                                    w2.data(), 2.0f, 5.0f, 5, reinterpret_cast<float*>(16),
+                                    nullptr, nullptr, nullptr) == UMI_ERR_UNSUPPORTED);
+    CHECK(g_prepass == before);
+}
+
 void check_copy_pool()
 {
     auto worker = [](int seed) {
@@ -276,6 +344,7 @@ int main(int argc, char** argv)
     CHECK(umi_set_tuning(nullptr) == UMI_OK);
     check_direct_batches();
     check_plans();
+    check_noalloc();
     check_copy_pool();
     umi_release();
     CHECK(fake_hip::live_device_blocks() == 0);
