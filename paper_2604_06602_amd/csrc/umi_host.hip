@@ -32,7 +32,7 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
                        int tile_count, uint32_t* counter, int grid, float* trend, float* median,
-                       hipStream_t stream);
+                       int feat, hipStream_t stream);
 
 namespace {
 
@@ -215,6 +215,7 @@ struct PackView {
     int64_t ntiles = 0;
     int64_t nchunks = 0;      // pre-pass chunks
     int gpc = kDefaultGroupsPerCU;  // persistent groups per CU
+    int feat = kFeatAll;      // estimate-kernel paths the batch needs (kFeat* bits)
 };
 
 // Tile sizes a batch too small to give every CU a tile falls back to, largest
@@ -298,6 +299,14 @@ umi_status pack_into(const int64_t* offsets, const int64_t* lengths, int64_t n, 
         out->ntiles += nt;
         out->nchunks += nch;
     }
+    // the estimate-kernel paths this batch needs
+    out->feat = o.scale == UMI_SCALE_MAD ? kFeatExtra : 0;
+    for (int64_t i = 0; i < nord; ++i) {
+        const CurveDesc& d = out->curves[i];
+        if (d.W <= kSmallW) out->feat |= kFeatSmall;
+        if (d.tile <= kSplitMaxTile) out->feat |= kFeatSplit;
+        if (d.window_days > 0.0) out->feat |= kFeatExtra;
+    }
     out->gpc = kDefaultGroupsPerCU;
     if (nord > 0) {
         int t_unused;
@@ -314,6 +323,7 @@ struct Packed {
     int64_t ntiles = 0;
     int64_t nchunks = 0;
     int gpc = kDefaultGroupsPerCU;
+    int feat = kFeatAll;
 };
 
 umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const int32_t* W,
@@ -332,6 +342,7 @@ umi_status pack(const int64_t* offsets, const int64_t* lengths, int64_t n, const
     out->ntiles = v.ntiles;
     out->nchunks = v.nchunks;
     out->gpc = v.gpc;
+    out->feat = v.feat;
     return UMI_OK;
 }
 
@@ -447,8 +458,8 @@ PrepLaunch prep_launch_for(int64_t ncurves, int64_t nchunks, int n_cu)
 hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, float* median,
                            const uint8_t* dblock, const DeviceBuffers& b, int mode,
                            const CurveDesc* table, const int64_t* curve_tiles, int ncurves,
-                           PrepLaunch prep, int main_grid, hipEvent_t ev0, hipEvent_t ev1,
-                           hipStream_t stream)
+                           PrepLaunch prep, int main_grid, int feat, hipEvent_t ev0,
+                           hipEvent_t ev1, hipStream_t stream)
 {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblock);
     const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
@@ -459,7 +470,7 @@ hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, 
             return e;
         if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, 0, -1, &b.ctr->queue, main_grid,
-                             trend, median, stream)) != hipSuccess)
+                             trend, median, feat, stream)) != hipSuccess)
             return e;
         if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
         return hipSuccess;
@@ -473,8 +484,7 @@ hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, 
             return e;
         const int nt = (int)curve_tiles[i];
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, table[i].tile_base, nt, nullptr,
-                             nt, trend, median, stream)) !=
-            hipSuccess)
+                             nt, trend, median, feat, stream)) != hipSuccess)
             return e;
     }
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return e;
@@ -620,7 +630,7 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     const int grid = (int)std::min<int64_t>(p.ntiles, (int64_t)p.gpc * cu_count(device));
     e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, p.curves.data(),
                         p.curve_tiles.data(), (int)nc,
-                        prep_launch_for(nc, p.nchunks, cu_count(device)), grid,
+                        prep_launch_for(nc, p.nchunks, cu_count(device)), grid, p.feat,
                         (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
@@ -910,7 +920,8 @@ umi_status detrend_batch(const float* flux, const double* time, const int64_t* l
     const int grid = (int)std::min<int64_t>(v.ntiles, (int64_t)v.gpc * n_cu);
     e = enqueue_kernels(flux, time, trend, median, base + kBlockOff, b, opt.mode, g_curves,
                         g_curve_tiles, (int)v.ncurves, prep_launch_for(v.ncurves, v.nchunks, n_cu),
-                        grid, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
+                        grid, v.feat, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop,
+                        stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -1133,7 +1144,8 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
         if (ce == hipSuccess)
             ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
                                       UMI_MODE_PERSISTENT, nullptr, nullptr, (int)cap_curves,
-                                      prep, p->main_grid, nullptr, nullptr, p->stream);
+                                      prep, p->main_grid, umi::kFeatAll, nullptr, nullptr,
+                                      p->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(p->stream, &g);
         if (ce != hipSuccess || e != hipSuccess) {

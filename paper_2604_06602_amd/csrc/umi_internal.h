@@ -14,6 +14,12 @@ constexpr int kWords = kStageMax / 64 + 1;  // bit-vector words incl. sentinel
 constexpr int kMainThreads = 512;            // threads per main-kernel workgroup
 constexpr int kMaxTile = 3 * kMainThreads;   // output positions per tile: <= 3 per lane
 constexpr int kSplitMaxTile = kMainThreads / 2;  // tiles this small split windows
+constexpr int kSmallW = 31;                  // full windows this small take register networks
+// Paths of the estimate kernel a batch needs (bits of a kernel instance).
+constexpr int kFeatSmall = 1;                // small-window networks (W <= kSmallW)
+constexpr int kFeatSplit = 2;                // split tiles (tile <= kSplitMaxTile)
+constexpr int kFeatExtra = 4;                // MAD ablation, time windows
+constexpr int kFeatAll = kFeatSmall | kFeatSplit | kFeatExtra;
 
 // Lanes that share one window for a tile of `tile` output positions: 1 above
 // kSplitMaxTile (each lane takes up to three windows), else the largest of 2,

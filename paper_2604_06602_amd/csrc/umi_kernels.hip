@@ -995,7 +995,6 @@ __device__ __forceinline__ float window_mad(const MainSmem& sm, int levels, uint
     return mad;
 }
 
-constexpr int kSmallW = 31;
 
 // Sort 32 keys in registers ascending (bitonic network).
 __device__ __forceinline__ void sort32(uint32_t (&k)[32])
@@ -1077,6 +1076,7 @@ __device__ __forceinline__ void small_window_medians(const uint32_t* __restrict_
 // The window of output position p: its valid samples are the compacted
 // positions [ca, ca + n) of the staged tile.  False when p is invalid or in a
 // dead segment (a NaN output).
+template <int kFeat>
 __device__ __forceinline__ bool window_range(const MainSmem& sm, const CurveDesc& cd,
                                              const int32_t* __restrict__ segid,
                                              const double* __restrict__ time, int h, int s0,
@@ -1108,7 +1108,7 @@ __device__ __forceinline__ bool window_range(const MainSmem& sm, const CurveDesc
         if (nx <= lim) lim = nx - 1u;
     }
     int b = s0 + (int)lim;
-    if (cd.window_days > 0.0) {
+    if ((kFeat & kFeatExtra) && cd.window_days > 0.0) {
         // time window: only the samples within half its length of p count.
         // Times are non-decreasing, so they form a run that two scans in from
         // the index window's ends find (invalid samples inside it are skipped
@@ -1170,7 +1170,7 @@ __device__ __forceinline__ void window_phase1(const MainSmem& sm, int levels, in
 }
 
 // The windows of one tile: each lane takes R consecutive output positions.
-template <int R>
+template <int R, int kFeat>
 __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int nv,
                                              const CurveDesc& cd, int h, int s0, int N, int t0,
                                              int t1,
@@ -1191,7 +1191,8 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         const int p = pfirst + r;
         ca[r] = 0;
         n[r] = 0;
-        live[r] = p < t1 && window_range(sm, cd, segid, time, h, s0, N, m_min, p, ca[r], n[r]);
+        live[r] = p < t1 &&
+                  window_range<kFeat>(sm, cd, segid, time, h, s0, N, m_min, p, ca[r], n[r]);
     }
     // The common case -- every window of the wave live, of one length, and
     // consecutive -- runs the fused loops with a wave-uniform trip count.
@@ -1308,7 +1309,7 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-template <int G>
+template <int G, int kFeat>
 __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int levels, int nv,
                                                    const CurveDesc& cd, int h, int s0, int N,
                                                    int t0, int t1,
@@ -1323,7 +1324,8 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
     const int l = (int)threadIdx.x & (G - 1);
     const int p = t0 + (int)threadIdx.x / G;
     uint32_t ca = 0, n = 0;
-    const bool live = p < t1 && window_range(sm, cd, segid, time, h, s0, N, m_min, p, ca, n);
+    const bool live =
+        p < t1 && window_range<kFeat>(sm, cd, segid, time, h, s0, N, m_min, p, ca, n);
     float m = 0.0f, sc = 0.0f;
     uint32_t nplus = 0;
     if (live) window_phase1(sm, levels, nv, scale, ca, n, m, sc, nplus);  // same on every lane
@@ -1366,6 +1368,12 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
     }
 }
 
+// kFeat (kFeat* bits) selects the paths an instance carries: the
+// small-window networks, split tiles, and the MAD ablation with time windows.
+// The host launches the smallest instance that covers the batch; fewer paths
+// leave the compiler more registers for the rest, and every instance gives
+// the same results on the batches it serves.
+template <int kFeat>
 __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const float* __restrict__ flux, const int32_t* __restrict__ segid,
     const BatchHeader* __restrict__ hdr,
@@ -1378,7 +1386,7 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const int lane = __lane_id();
     const int wave = tid >> 6;
     const int iters = hdr->iters;
-    const int scale = hdr->scale;
+    const int scale = (kFeat & kFeatExtra) ? hdr->scale : (int)UMI_SCALE_UPPER_RMS;
     float* const detrended = hdr->detrended;
     const double* const time = hdr->time;
     // tile range [tile_first, tile_end): a count < 0 means "all tiles of the batch"
@@ -1419,8 +1427,10 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             const int i = i0 + lane;
             const int sgi = i < N ? sg[i] : sg0;
             const bool ok = (i < N) && (sgi != -1);
-            const int segi = i < N ? (sgi >= 0 ? sgi : (sgi == -1 ? -1 : s0 + i)) : seg0;
-            same = same && segi == seg0;
+            if (kFeat & kFeatSmall) {
+                const int segi = i < N ? (sgi >= 0 ? sgi : (sgi == -1 ? -1 : s0 + i)) : seg0;
+                same = same && segi == seg0;
+            }
             const uint64_t bal = __ballot(ok);
             const uint64_t st = __ballot(ok && sgi <= -2);
             if (lane == 0) {
@@ -1428,10 +1438,15 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
                 sm.sbits[i0 >> 6] = st;
             }
         }
-        const int G = split_lanes(cd.tile);  // lanes per window (1: R windows per lane)
-        const bool simple = __syncthreads_and(same) && seg0 >= 0 && cd.W <= kSmallW &&
-                            scale != UMI_SCALE_MAD && cd.window_days == 0.0 && t0 >= h &&
-                            t1 + h <= cd.len && G == 1;
+        // lanes per window (1: R windows per lane)
+        const int G = (kFeat & kFeatSplit) ? split_lanes(cd.tile) : 1;
+        bool simple = false;
+        if (kFeat & kFeatSmall)
+            simple = __syncthreads_and(same) && seg0 >= 0 && cd.W <= kSmallW &&
+                     scale != UMI_SCALE_MAD && cd.window_days == 0.0 && t0 >= h &&
+                     t1 + h <= cd.len && G == 1;
+        else
+            __syncthreads();
         word_prefix(sm.vbits, sm.vpre, nwv, reinterpret_cast<uint32_t*>(&sm.nvalid));
         __syncthreads();
         const int nv = sm.nvalid;
@@ -1521,15 +1536,15 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 
         // --- the tile's windows: G lanes per position, or R consecutive
         // positions per lane ---
-        if (G > 1) {
+        if ((kFeat & kFeatSplit) && G > 1) {
             if (G == 2)
-                tile_windows_split<2>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                tile_windows_split<2, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
                                       scale, time, trend, median, detrended);
             else if (G == 4)
-                tile_windows_split<4>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                tile_windows_split<4, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
                                       scale, time, trend, median, detrended);
             else
-                tile_windows_split<8>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
+                tile_windows_split<8, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
                                       scale, time, trend, median, detrended);
             __syncthreads();
             continue;
@@ -1552,13 +1567,13 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
         }
         if (R == 3)
-            tile_windows<3>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
+            tile_windows<3, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         else if (R == 2)
-            tile_windows<2>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
+            tile_windows<2, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         else
-            tile_windows<1>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
+            tile_windows<1, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters, scale,
                             simple, pm, pn, time, trend, median, detrended);
         __syncthreads();
     }
@@ -1588,11 +1603,22 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
                        int tile_count, uint32_t* counter, int grid, float* trend, float* median,
-                       hipStream_t stream)
+                       int feat, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(umi_main_kernel, dim3(grid), dim3(kMainThreads), 0, stream, flux, segid,
-                       hdr, curves, tiles, tile_first, tile_count, counter, trend, median);
+#define UMI_LAUNCH_MAIN(F)                                                                      \
+    hipLaunchKernelGGL(umi_main_kernel<F>, dim3(grid), dim3(kMainThreads), 0, stream, flux, segid, \
+                       hdr, curves, tiles, tile_first, tile_count, counter, trend, median)
+    // the instances built: none, small windows, split tiles, everything
+    if (feat == 0)
+        UMI_LAUNCH_MAIN(0);
+    else if (feat == kFeatSmall)
+        UMI_LAUNCH_MAIN(kFeatSmall);
+    else if (feat == kFeatSplit)
+        UMI_LAUNCH_MAIN(kFeatSplit);
+    else
+        UMI_LAUNCH_MAIN(kFeatAll);
+#undef UMI_LAUNCH_MAIN
     return hipGetLastError();
 }
 

@@ -104,7 +104,7 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
                        int tile_count, uint32_t* counter, int grid, float* trend, float* median,
-                       hipStream_t)
+                       int feat, hipStream_t)
 {
     ++g_main;
     CHECK(grid >= 1);
@@ -120,6 +120,10 @@ hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeade
         CHECK(t0 >= 0 && t0 < cd.len && t0 % cd.tile == 0);
         const int s0 = std::max(t0 - h, 0), s1 = std::min(t1 + h, cd.len);
         CHECK(s1 - s0 <= kStageMax);
+        // an instance without a path serves no tile that needs it
+        if (!(feat & kFeatSmall)) CHECK(cd.W > kSmallW);
+        if (!(feat & kFeatSplit)) CHECK(cd.tile > kSplitMaxTile);
+        if (!(feat & kFeatExtra)) CHECK(cd.window_days == 0.0 && hdr->scale == UMI_SCALE_UPPER_RMS);
         CHECK(split_lanes(cd.tile) * std::min(cd.tile, kMainThreads) <= kMainThreads ||
               split_lanes(cd.tile) == 1);
         volatile float fs = 0.0f;
