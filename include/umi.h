@@ -205,12 +205,14 @@ umi_status umi_detrend_gather_ex(const float* flux, const double* time,
 /*
  * Plans: a replayable launch over fixed device arrays, for serving loops.
  * umi_plan_create binds the arrays (each `capacity` samples; time and median
- * may be NULL) and a non-default stream, and allocates the plan's workspace
- * once.  umi_plan_run stages one batch -- curves at explicit offsets inside
+ * may be NULL) and a non-default stream, allocates the plan's workspace once
+ * and captures its hipGraphs: per staging slot one for batches of at most 256
+ * pre-pass chunks (512k samples) and one for any batch, each a copy of the
+ * staged tile table, the segmentation pre-pass and the persistent estimate
+ * kernel.  umi_plan_run stages one batch -- curves at explicit offsets inside
  * the arrays, as for umi_detrend_gather, at most `max_curves` curves with
  * W <= max_W -- into one of two pinned staging slots and replays that slot's
- * hipGraph (copy of the staged tile table, segmentation pre-pass, persistent
- * estimate kernel; captured on the slot's first use) on the plan's stream.
+ * graph for the batch's size on the plan's stream.
  * It allocates no device or pinned memory and returns without synchronising,
  * except that it waits for the replay that used the same slot two calls earlier.  Results
  * of a run are in `trend` / `median` once the stream reaches that point.

@@ -41,6 +41,7 @@ umi_status umi_host_copy_many(void* const* dst, const void* const* src, const in
 
 #define UMI_COPY_H2D 1
 #define UMI_COPY_D2H 2
+#define UMI_COPY_KERNEL 4 /* or-ed into kind: see umi_copy_async */
 
 /* Asynchronous host/device copies on `stream` (a hipStream_t, NULL = the
  * legacy default stream): for i in [0, n), bytes[i] bytes from src[i] to
@@ -51,6 +52,15 @@ umi_status umi_host_copy_many(void* const* dst, const void* const* src, const in
  * caller keeps every buffer alive, and the host buffers untouched, until the
  * stream work completes.  For the serving loop: the copies of a whole step in
  * one call.
+ * With UMI_COPY_KERNEL or-ed into kind, the copies run as a kernel on
+ * `stream` (one launch per 64 copies, one workgroup per 32 KiB piece) that
+ * reads and writes the host buffers directly over the bus, instead of being
+ * handed to the runtime's copy engines, whose enqueue has been seen to block
+ * the calling thread for several milliseconds now and then.  The host side
+ * of every copy must then be pinned memory from hipHostMalloc (as torch's
+ * pinned tensors are), which the device reaches at its host address;
+ * pageable memory is not allowed on this path.  Copies of one call must not
+ * overlap.
  * Errors: n < 0, an unknown kind, a NULL array with n > 0, a negative size or
  * a NULL pointer with a positive size give UMI_ERR_INVALID_ARG before anything
  * is enqueued; a failing enqueue gives UMI_ERR_DEVICE (copies before it stay

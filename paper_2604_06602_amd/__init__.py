@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     copy_async,
     COPY_H2D,
     COPY_D2H,
+    COPY_KERNEL,
     last_error,
     release,
     set_tuning,

@@ -136,13 +136,15 @@ def host_copy_many(dst_ptrs, src_ptrs, nbytes, threads: int = 1):
                                   int(threads)))
 
 
-COPY_H2D, COPY_D2H = 1, 2
+COPY_H2D, COPY_D2H, COPY_KERNEL = 1, 2, 4
 
 
 def copy_async(dst_ptrs, src_ptrs, nbytes, kind: int, stream=None):
     """Enqueue host<->device copies (kind COPY_H2D or COPY_D2H) of nbytes[i]
     from src_ptrs[i] to dst_ptrs[i] on `stream` (a torch stream, a raw
-    hipStream_t address, or None for the current stream) in one native call."""
+    hipStream_t address, or None for the current stream) in one native call.
+    With COPY_KERNEL or-ed into kind the copies run as a kernel that reaches
+    the (pinned) host buffers directly instead of through the copy engines."""
     d = np.ascontiguousarray(dst_ptrs, np.uint64)
     s = np.ascontiguousarray(src_ptrs, np.uint64)
     b = np.ascontiguousarray(nbytes, np.int64)

@@ -29,6 +29,7 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
                           const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
                           hipStream_t stream);
+hipError_t launch_copy(const CopyBatch& cb, hipStream_t stream);
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
                        int tile_count, uint32_t* counter, int grid, float* trend, float* median,
@@ -785,6 +786,50 @@ void plan_free(umi_plan* p)
     p->buf.release();
 }
 
+// Curves the staged table of a graph kind holds, and that kind's pre-pass:
+// kind 0 serves batches of at most kPrepSmallChunks chunks with the chunked
+// pre-pass over that many workgroups (each curve has a chunk, so the table
+// holds at most that many curves); kind 1 any batch, with the curve walker,
+// one workgroup per possible curve.
+int64_t plan_kind_curves(const umi_plan* p, int kind)
+{
+    return kind == 0 ? std::min<int64_t>(p->max_curves, umi::kPrepSmallChunks) : p->max_curves;
+}
+
+umi::PrepLaunch plan_kind_prep(const umi_plan* p, int kind)
+{
+    return kind == 0 ? umi::PrepLaunch{false, umi::kPrepSmallChunks}
+                     : umi::PrepLaunch{true, (int)p->max_curves};
+}
+
+// Capture slot `si`'s graph of `kind`: the copy of the staged block, the
+// pre-pass and the persistent estimate kernel.  Nothing runs during capture.
+hipError_t plan_capture(umi_plan* p, int si, int kind)
+{
+    umi_plan::Slot& s = p->slot[si];
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(plan_kind_curves(p, kind)),
+                                   hipMemcpyHostToDevice, p->stream);
+    if (ce == hipSuccess)
+        ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
+                                  UMI_MODE_PERSISTENT, nullptr, nullptr,
+                                  (int)plan_kind_curves(p, kind), plan_kind_prep(p, kind),
+                                  p->main_grid, umi::kFeatAll, nullptr, nullptr, p->stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->stream, &g);
+    if (ce != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return ce != hipSuccess ? ce : e;
+    }
+    s.graph[kind] = g;
+    if ((e = hipGraphInstantiate(&s.exec[kind], g, nullptr, nullptr, 0)) != hipSuccess) {
+        s.exec[kind] = nullptr;
+        return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1079,6 +1124,14 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
     int t_unused, gpc;
     umi::tuned(max_W, -1, &t_unused, &gpc);
     p->main_grid = gpc * umi::cu_count(p->device);
+    // every slot's graphs of both kinds, now rather than on a serving step
+    for (int si = 0; si < 2 && e == hipSuccess; ++si)
+        for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) e = plan_capture(p, si, kind);
+    if (e != hipSuccess) {
+        plan_free(p);
+        delete p;
+        return umi::fail_hip(e, "graph capture");
+    }
     *out = p;
     return UMI_OK;
 }
@@ -1126,38 +1179,10 @@ umi_status umi_plan_run_ex(umi_plan* p, const int64_t* offsets, const int64_t* l
     }
     umi::write_block(s.host, pk.curves.data(), (int64_t)pk.curves.size(), pk.ntiles, pk.nchunks,
                      iters, o, p->time);
-    // small batches: the chunked pre-pass over kPrepSmallChunks workgroups
-    // (each curve has a chunk, so the table holds at most that many curves);
-    // larger ones: the curve walker, one workgroup per possible curve
+    // small batches (at most kPrepSmallChunks chunks) replay kind 0
     const int kind = pk.nchunks <= umi::kPrepSmallChunks ? 0 : 1;
-    const int64_t cap_curves =
-        kind == 0 ? std::min<int64_t>(p->max_curves, umi::kPrepSmallChunks) : p->max_curves;
-    const umi::PrepLaunch prep = kind == 0 ? umi::PrepLaunch{false, umi::kPrepSmallChunks}
-                                           : umi::PrepLaunch{true, (int)p->max_curves};
-    if (!s.exec[kind]) {
-        // capture once per slot and kind: copy of the staged block, pre-pass
-        // over cap_curves (blocks beyond the batch exit), persistent estimate
-        if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return umi::fail_hip(e, "hipStreamBeginCapture");
-        hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(cap_curves),
-                                       hipMemcpyHostToDevice, p->stream);
-        if (ce == hipSuccess)
-            ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
-                                      UMI_MODE_PERSISTENT, nullptr, nullptr, (int)cap_curves,
-                                      prep, p->main_grid, umi::kFeatAll, nullptr, nullptr,
-                                      p->stream);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(p->stream, &g);
-        if (ce != hipSuccess || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return umi::fail_hip(ce != hipSuccess ? ce : e, "graph capture");
-        }
-        s.graph[kind] = g;
-        if ((e = hipGraphInstantiate(&s.exec[kind], g, nullptr, nullptr, 0)) != hipSuccess) {
-            s.exec[kind] = nullptr;
-            return umi::fail_hip(e, "hipGraphInstantiate");
-        }
-    }
+    if (!s.exec[kind] && (e = plan_capture(p, p->next, kind)) != hipSuccess)
+        return umi::fail_hip(e, "graph capture");
     if ((e = hipGraphLaunch(s.exec[kind], p->stream)) != hipSuccess)
         return umi::fail_hip(e, "hipGraphLaunch");
     if ((e = hipEventRecord(s.done, p->stream)) != hipSuccess)
@@ -1297,6 +1322,8 @@ umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_
                           int64_t n, int32_t kind, void* stream)
 {
     if (n < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: n < 0");
+    const bool by_kernel = (kind & UMI_COPY_KERNEL) != 0;
+    kind &= ~UMI_COPY_KERNEL;
     if (kind != UMI_COPY_H2D && kind != UMI_COPY_D2H)
         return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: unknown kind");
     if (n == 0) return UMI_OK;
@@ -1305,6 +1332,54 @@ umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_
         if (bytes[i] < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: bytes < 0");
         if (bytes[i] > 0 && (!dst[i] || !src[i]))
             return umi::fail(UMI_ERR_INVALID_ARG, "umi_copy_async: NULL pointer");
+    }
+    if (by_kernel) {
+        // every host range must be pinned host memory the device can reach:
+        // the copy kernel reads and writes it at its device address
+        std::vector<void*> hdev((size_t)n, nullptr);
+        for (int64_t i = 0; i < n; ++i) {
+            if (bytes[i] == 0) continue;
+            char* h = static_cast<char*>(kind == UMI_COPY_H2D ? const_cast<void*>(src[i]) : dst[i]);
+            for (int end = 0; end < 2; ++end) {
+                char* q = end ? h + bytes[i] - 1 : h;
+                hipPointerAttribute_t a;
+                const hipError_t e = hipPointerGetAttributes(&a, q);
+                if (e != hipSuccess) (void)hipGetLastError();  // not sticky for later calls
+                if (e != hipSuccess || a.type != hipMemoryTypeHost || !a.devicePointer ||
+                    !a.hostPointer)
+                    return umi::fail(UMI_ERR_INVALID_ARG,
+                                     "umi_copy_async: with UMI_COPY_KERNEL the host side of every "
+                                     "copy must be pinned host memory (hipHostMalloc)");
+                if (!end)
+                    hdev[(size_t)i] = static_cast<char*>(a.devicePointer) +
+                                      (q - static_cast<char*>(a.hostPointer));
+            }
+        }
+        // lists of at most kCopyMax copies, each as one launch of the copy kernel
+        umi::CopyBatch cb;
+        std::memset(&cb, 0, sizeof cb);
+        int64_t pieces = 0;
+        for (int64_t i = 0; i <= n; ++i) {
+            const bool full = cb.n == umi::kCopyMax ||
+                              (i < n && pieces + (bytes[i] + umi::kCopyPieceBytes - 1) /
+                                                     umi::kCopyPieceBytes > (int64_t)INT32_MAX);
+            if ((i == n || full) && cb.n > 0) {
+                cb.first[cb.n] = (int32_t)pieces;
+                const hipError_t e = umi::launch_copy(cb, static_cast<hipStream_t>(stream));
+                if (e != hipSuccess) return umi::fail_hip(e, "umi_copy_async: copy kernel");
+                std::memset(&cb, 0, sizeof cb);
+                pieces = 0;
+            }
+            if (i == n) break;
+            if (bytes[i] == 0) continue;
+            cb.first[cb.n] = (int32_t)pieces;
+            cb.src[cb.n] = static_cast<const uint8_t*>(kind == UMI_COPY_H2D ? hdev[(size_t)i] : src[i]);
+            cb.dst[cb.n] = static_cast<uint8_t*>(kind == UMI_COPY_D2H ? hdev[(size_t)i] : dst[i]);
+            cb.bytes[cb.n] = bytes[i];
+            pieces += (bytes[i] + umi::kCopyPieceBytes - 1) / umi::kCopyPieceBytes;
+            ++cb.n;
+        }
+        return UMI_OK;
     }
     const hipMemcpyKind k = kind == UMI_COPY_H2D ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
     for (int64_t i = 0; i < n; ++i) {

@@ -111,6 +111,23 @@ struct Counters {
 };
 static_assert(sizeof(Counters) == 32, "Counters layout");
 
+// A list of copies for the copy kernel, passed by value as kernel arguments
+// (so nothing on either side needs to outlive the launch): copy i moves
+// bytes[i] bytes from src[i] to dst[i] and is cut into pieces of kCopyPieceBytes
+// bytes, piece p of the launch belonging to the copy i with
+// first[i] <= p < first[i + 1].
+constexpr int kCopyMax = 64;
+constexpr int kCopyPieceBytes = 32768;
+struct CopyBatch {
+    int32_t n;                   // copies
+    int32_t reserved;
+    int32_t first[kCopyMax + 1]; // first piece of each copy; first[n] = pieces
+    const uint8_t* src[kCopyMax];
+    uint8_t* dst[kCopyMax];
+    int64_t bytes[kCopyMax];
+};
+static_assert(sizeof(CopyBatch) <= 2048, "CopyBatch fits the kernel arguments");
+
 // Per-sample segment word written by the pre-pass at segid[curve.off + i]:
 //   -1       sample i is invalid;
 //   x >= 0   sample i is valid and its segment starts at the valid sample x

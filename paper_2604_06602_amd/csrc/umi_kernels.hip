@@ -1580,6 +1580,42 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Copy kernel (serving helper, not a step of the method): one workgroup per
+// piece of a list of copies between device memory and pinned host memory,
+// read and written directly over the bus rather than through the runtime's
+// copy engines.
+
+__global__ __launch_bounds__(256) void umi_copy_kernel(CopyBatch cb)
+{
+    __shared__ int sh_copy;
+    const int piece = (int)blockIdx.x;
+    if (threadIdx.x < 64) {  // the copy this piece belongs to: last i with first[i] <= piece
+        const int lane = (int)threadIdx.x;
+        const bool le = lane < cb.n && cb.first[lane] <= piece;
+        const uint64_t m = __ballot(le);  // lane 0 always qualifies
+        if (lane == 0) sh_copy = 63 - __builtin_clzll(m);
+    }
+    __syncthreads();
+    const int i = sh_copy;
+    const int64_t off = (int64_t)(piece - cb.first[i]) * kCopyPieceBytes;
+    const int64_t len = min((int64_t)kCopyPieceBytes, cb.bytes[i] - off);
+    const uint8_t* src = cb.src[i] + off;
+    uint8_t* dst = cb.dst[i] + off;
+    const uintptr_t align = (uintptr_t)src | (uintptr_t)dst | (uintptr_t)len;
+    if ((align & 15u) == 0) {
+        const uint4* s4 = reinterpret_cast<const uint4*>(src);
+        uint4* d4 = reinterpret_cast<uint4*>(dst);
+        for (int64_t k = threadIdx.x; k < len / 16; k += blockDim.x) d4[k] = s4[k];
+    } else if ((align & 3u) == 0) {
+        const uint32_t* s1 = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* d1 = reinterpret_cast<uint32_t*>(dst);
+        for (int64_t k = threadIdx.x; k < len / 4; k += blockDim.x) d1[k] = s1[k];
+    } else {
+        for (int64_t k = threadIdx.x; k < len; k += blockDim.x) dst[k] = src[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch wrappers (the host library calls only these).
 
 hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
@@ -1597,6 +1633,14 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
         hipLaunchKernelGGL((umi_prepass_chunk_kernel<kPrepThreads, kPrepItems>), dim3(grid),
                            dim3(kPrepThreads), 0, stream, flux, time, hdr, curves, curve_one,
                            segid, tiles, ctr, recs, clear_queue ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const CopyBatch& cb, hipStream_t stream)
+{
+    const int pieces = cb.first[cb.n];
+    if (pieces <= 0) return hipSuccess;
+    hipLaunchKernelGGL(umi_copy_kernel, dim3(pieces), dim3(256), 0, stream, cb);
     return hipGetLastError();
 }
 

@@ -308,7 +308,11 @@ class GpuExecutor:
         self.copy_threads = max(1, int(copy_threads))
         self._copy = _lib.host_copy_many
         self._copy_async = _lib.copy_async
-        self._H2D, self._D2H = _lib.COPY_H2D, _lib.COPY_D2H
+        # the rings are pinned, so the copies run as a kernel that reaches
+        # them directly: enqueues through the runtime's copy engines have
+        # blocked the scheduler thread for several milliseconds now and then
+        self._H2D = _lib.COPY_H2D | _lib.COPY_KERNEL
+        self._D2H = _lib.COPY_D2H | _lib.COPY_KERNEL
         self._flux_ptr = self.flux.data_ptr()
         self._time_ptr = self.time.data_ptr()
         self._trend_ptr = self.trend.data_ptr()
@@ -316,7 +320,14 @@ class GpuExecutor:
         self.pinned_fallbacks = 0  # one-off pinned blocks taken because a ring was full
         # seconds spent in each part of staging and launching (diagnostics)
         self.phase_s = {"stage_alloc": 0.0, "stage_list": 0.0, "stage_copy": 0.0,
-                        "h2d": 0.0, "launch_plan": 0.0, "d2h": 0.0, "results": 0.0}
+                        "h2d": 0.0, "h2d_enqueue": 0.0, "h2d_event": 0.0, "launch_plan": 0.0,
+                        "d2h": 0.0, "results": 0.0}
+        self.phase_max_s = dict.fromkeys(self.phase_s, 0.0)  # longest single call of each
+
+    def _phase(self, name, dt):
+        self.phase_s[name] += dt
+        if dt > self.phase_max_s[name]:
+            self.phase_max_s[name] = dt
 
     def _pinned(self, ring, nbytes):
         got = ring.alloc(nbytes)
@@ -336,7 +347,6 @@ class GpuExecutor:
         ring block, which is released when its step completes (every group's
         copy is done by then: the steps wait on the shared event)."""
         clk = _time.perf_counter
-        ph = self.phase_s
         if not groups:
             return []
         t0 = clk()
@@ -362,13 +372,16 @@ class GpuExecutor:
         t3 = clk()
         self._copy_async(h_dst.astype(np.uint64), h_src.astype(np.uint64), h_nb, self._H2D,
                          self._copy_stream_ptr)
+        t3b = clk()
         ev = self.torch.cuda.Event()
         ev.record(self.copy_stream)
         t4 = clk()
-        ph["stage_alloc"] += t1 - t0
-        ph["stage_list"] += t2 - t1
-        ph["stage_copy"] += t3 - t2
-        ph["h2d"] += t4 - t3
+        self._phase("h2d_enqueue", t3b - t3)
+        self._phase("h2d_event", t4 - t3b)
+        self._phase("stage_alloc", t1 - t0)
+        self._phase("stage_list", t2 - t1)
+        self._phase("stage_copy", t3 - t2)
+        self._phase("h2d", t4 - t3)
         return [(ev, tok, tbuf)] + [(ev, None, None)] * (len(groups) - 1)
 
     def stage_upload(self, offset: int, parts):
@@ -415,8 +428,8 @@ class GpuExecutor:
         self._copy_async(dst, src, nbytes, self._D2H, self._copy_stream_ptr)
         done = torch.cuda.Event()
         done.record(self.copy_stream)
-        self.phase_s["launch_plan"] += t1 - t0
-        self.phase_s["d2h"] += _time.perf_counter() - t1
+        self._phase("launch_plan", t1 - t0)
+        self._phase("d2h", _time.perf_counter() - t1)
         return (done, outs, [u[1] for u in uploads])
 
     def ready(self, handle) -> bool:
@@ -436,7 +449,7 @@ class GpuExecutor:
         for tok in handle[2]:  # the step is done, so its uploads are too
             if tok is not None:
                 self.ring_in.release(tok)
-        self.phase_s["results"] += _time.perf_counter() - t0
+        self._phase("results", _time.perf_counter() - t0)
         return res
 
     def close(self):
@@ -582,16 +595,20 @@ class Server:
             ph = getattr(self.ex, "phase_s", None)
             if ph is not None:
                 out["executor_phase_s"] = dict(ph)
+            pm = getattr(self.ex, "phase_max_s", None)
+            if pm is not None:
+                out["executor_phase_max_ms"] = {k: v * 1e3 for k, v in pm.items()}
             return out
 
     def reset_stats(self):
         """Start a new measurement window (e.g. after a warm-up)."""
         with self._lock:
             self.stats = Stats()
-            ph = getattr(self.ex, "phase_s", None)
-            if ph is not None:
-                for k in ph:
-                    ph[k] = 0.0
+            for name in ("phase_s", "phase_max_s"):
+                ph = getattr(self.ex, name, None)
+                if ph is not None:
+                    for k in ph:
+                        ph[k] = 0.0
             self.arena.high_water = self.arena.used
 
     # -- scheduler ---------------------------------------------------------

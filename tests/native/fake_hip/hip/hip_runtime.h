@@ -127,6 +127,27 @@ inline hipError_t hipGraphDestroy(hipGraph_t g)
     delete[] reinterpret_cast<char*>(g);
     return hipSuccess;
 }
+enum hipMemoryType { hipMemoryTypeUnregistered = 0, hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2 };
+struct hipPointerAttribute_t {
+    enum hipMemoryType type;
+    int device;
+    void* devicePointer;
+    void* hostPointer;
+    int isManaged;
+    unsigned allocationFlags;
+};
+// every pointer counts as pinned host memory reachable at its own address
+inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p)
+{
+    a->type = hipMemoryTypeHost;
+    a->device = 0;
+    a->devicePointer = const_cast<void*>(p);
+    a->hostPointer = const_cast<void*>(p);
+    a->isManaged = 0;
+    a->allocationFlags = 0;
+    return hipSuccess;
+}
+inline hipError_t hipGetLastError() { return hipSuccess; }
 template <class T>
 inline hipError_t hipGetSymbolAddress(void** p, T sym)
 {

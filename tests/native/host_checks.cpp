@@ -99,6 +99,18 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
     return hipSuccess;
 }
 
+// The copy kernel: each copy of the list is done in full, and the pieces
+// count matches the sizes.
+hipError_t launch_copy(const CopyBatch& cb, hipStream_t)
+{
+    CHECK(cb.n >= 1 && cb.n <= kCopyMax);
+    for (int i = 0; i < cb.n; ++i) {
+        CHECK(cb.first[i + 1] - cb.first[i] == (cb.bytes[i] + kCopyPieceBytes - 1) / kCopyPieceBytes);
+        std::memcpy(cb.dst[i], cb.src[i], (size_t)cb.bytes[i]);
+    }
+    return hipSuccess;
+}
+
 // The estimate kernel: every tile of its range lies in its curve, its
 // staged span fits the workgroup, and the outputs of its positions exist.
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
@@ -311,6 +323,30 @@ void check_noalloc()
     CHECK(g_prepass == before);
 }
 
+// Host/device copy lists through the copy kernel's launcher: lists longer
+// than one launch holds, zero sizes mixed in, every byte arrives.
+void check_copy_kernel_lists()
+{
+    for (int round = 0; round < 20; ++round) {
+        const int n = (int)uni(0, 200);
+        std::vector<std::vector<char>> src((size_t)n), dst((size_t)n);
+        std::vector<void*> d((size_t)n);
+        std::vector<const void*> sp((size_t)n);
+        std::vector<int64_t> bytes((size_t)n);
+        for (int i = 0; i < n; ++i) {
+            bytes[i] = uni(0, 3) == 0 ? 0 : uni(1, 100000);
+            src[i].assign((size_t)bytes[i], (char)(i * 7 + round));
+            dst[i].assign((size_t)bytes[i], 0);
+            d[i] = dst[i].data();
+            sp[i] = src[i].data();
+        }
+        CHECK(umi_copy_async(d.data(), sp.data(), bytes.data(), n,
+                             (int32_t)(uni(0, 1) ? UMI_COPY_H2D : UMI_COPY_D2H) | UMI_COPY_KERNEL,
+                             nullptr) == UMI_OK);
+        for (int i = 0; i < n; ++i) CHECK(dst[i] == src[i]);
+    }
+}
+
 void check_copy_pool()
 {
     auto worker = [](int seed) {
@@ -349,6 +385,7 @@ int main(int argc, char** argv)
     check_direct_batches();
     check_plans();
     check_noalloc();
+    check_copy_kernel_lists();
     check_copy_pool();
     umi_release();
     CHECK(fake_hip::live_device_blocks() == 0);

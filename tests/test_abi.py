@@ -304,7 +304,9 @@ def test_copy_async_rejects_bad_arguments(lib):
     made here: every case fails validation, and n = 0 is a no-op)."""
     a = np.ones(8, np.uint8)
     lib.copy_async([], [], [], lib.COPY_H2D, 0)
-    for bad in [dict(kind=0), dict(kind=3), dict(nbytes=[-1]), dict(dst=[0]), dict(src=[0])]:
+    for bad in [dict(kind=0), dict(kind=3), dict(kind=lib.COPY_KERNEL), dict(kind=3 | lib.COPY_KERNEL),
+                dict(kind=8 | lib.COPY_D2H), dict(nbytes=[-1]), dict(dst=[0]), dict(src=[0]),
+                dict(nbytes=[-1], kind=lib.COPY_D2H | lib.COPY_KERNEL)]:
         args = dict(dst=[a.ctypes.data], src=[a.ctypes.data], nbytes=[8], kind=lib.COPY_D2H)
         args.update(bad)
         with pytest.raises(lib.UmiError):

@@ -72,13 +72,20 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
         assert rel.max() <= 1e-5
 
 
-def test_copy_async_round_trip(torch):
+@pytest.mark.parametrize("by_kernel", [False, True], ids=["copy_engine", "copy_kernel"])
+def test_copy_async_round_trip(torch, by_kernel):
     """The serving loop's batched host<->device copies: a ragged list of
     pinned-host ranges up to the device and back on one stream, every byte
-    where it belongs and nothing written past the ranges."""
+    where it belongs and nothing written past the ranges -- through the
+    runtime's copy engines, and as the copy kernel (odd sizes and offsets take
+    its byte path, aligned ones its 16-byte path, and more than 64 copies
+    take several launches)."""
     import paper_2604_06602_amd as umi
     rng = np.random.default_rng(9)
     sizes = [0, 1, 4096, 1 << 20, 3 * (1 << 20) + 5]
+    if by_kernel:
+        sizes = sizes + [int(v) for v in rng.integers(0, 70000, 90)] + [16, 32768, 32769]
+    flag = umi.COPY_KERNEL if by_kernel else 0
     total = sum(sizes)
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     host = torch.empty(total, dtype=torch.uint8, pin_memory=True)
@@ -88,9 +95,9 @@ def test_copy_async_round_trip(torch):
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
     umi.copy_async([dev.data_ptr() + int(o) for o in offs], [host.data_ptr() + int(o) for o in offs],
-                   sizes, umi.COPY_H2D, s)
+                   sizes, umi.COPY_H2D | flag, s)
     umi.copy_async([back.data_ptr() + int(o) for o in offs], [dev.data_ptr() + int(o) for o in offs],
-                   sizes, umi.COPY_D2H, s)
+                   sizes, umi.COPY_D2H | flag, s)
     s.synchronize()
     assert torch.equal(back, host)
     assert not dev[total:].any().item()
