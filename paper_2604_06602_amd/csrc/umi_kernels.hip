@@ -844,6 +844,31 @@ __device__ __forceinline__ void bisquare_acc(float x, float k, float b, float be
     swv = __builtin_fmaf(w, v, swv);
 }
 
+// Eq. 4 in residual form: mu + sum(w v) / (k sum(w)), with a correctly
+// rounded division.  Every path uses this same expression, so paths that sum
+// in the same order agree bit for bit.  (The hardware reciprocal would do
+// here too -- the quotient is a correction of the order of the scale -- but
+// it changed the register assignment of the estimate loops for the worse.)
+__device__ __forceinline__ float mu_update(float mu, float swv, float sw, float k)
+{
+    return mu + swv / (sw * k);
+}
+
+// Eq. 1: s = 0.6745 sqrt(ssq / n+), with the hardware square root and
+// reciprocal (1 ulp each): once per window, in place of a correctly rounded
+// square root and division that cost some 30 instructions (7 % of the
+// estimate kernel's time at W = 25).
+__device__ __forceinline__ float upper_scale(float ssq, uint32_t nplus)
+{
+    return kScaleConst * __builtin_amdgcn_sqrtf(ssq * __builtin_amdgcn_rcpf((float)nplus));
+}
+
+// The scaled variable's factor k = A / (c s) (A = (1 + alpha) / 2).
+__device__ __forceinline__ float bisquare_k(float kA, float c, float s)
+{
+    return kA * __builtin_amdgcn_rcpf(c * s);
+}
+
 // Phase 3 over the n samples xv[c0], ..., xv[c0 + n - 1] of one window, from
 // the median m with the scaled k above.  The samples are summed in index
 // order whatever the launch shape, so results do not depend on the tiling.
@@ -860,7 +885,7 @@ __device__ __forceinline__ float bisquare(const float* __restrict__ xv, int c0, 
 #pragma unroll 8
         for (int j = 0; j < n; ++j) bisquare_acc(x[j], k, b, beta, sw, swv);
         if (!(sw > 0.0f)) break;  // no weight left: keep mu
-        mu = mu + swv / (sw * k);
+        mu = mu_update(mu, swv, sw, k);
     }
     return mu;
 }
@@ -916,7 +941,7 @@ __device__ __forceinline__ void bisquare_multi(const float* __restrict__ x, int 
         for (int r = 0; r < R; ++r) {
             if (act[r]) {
                 if (sw[r] > 0.0f)
-                    mu[r] = mu[r] + swv[r] / (sw[r] * k[r]);
+                    mu[r] = mu_update(mu[r], swv[r], sw[r], k[r]);
                 else
                     act[r] = false;  // no weight left: keep mu from now on
             }
@@ -1191,8 +1216,17 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         const int p = pfirst + r;
         ca[r] = 0;
         n[r] = 0;
-        live[r] = p < t1 &&
-                  window_range<kFeat>(sm, cd, segid, time, h, s0, N, m_min, p, ca[r], n[r]);
+        if ((kFeat & kFeatSmall) && simple) {
+            // a small-window tile: the whole span is valid and in one live
+            // segment, so every window is full and its compacted range is its
+            // staged range
+            live[r] = p < t1;
+            ca[r] = (uint32_t)(p - h - s0);
+            n[r] = (uint32_t)cd.W;
+        } else {
+            live[r] = p < t1 &&
+                      window_range<kFeat>(sm, cd, segid, time, h, s0, N, m_min, p, ca[r], n[r]);
+        }
     }
     // The common case -- every window of the wave live, of one length, and
     // consecutive -- runs the fused loops with a wave-uniform trip count.
@@ -1228,7 +1262,7 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (nplus[r] > 0) sc[r] = kScaleConst * __builtin_sqrtf(ssq[r] / (float)nplus[r]);
+            if (nplus[r] > 0) sc[r] = upper_scale(ssq[r], nplus[r]);
     }
     float k[R], mu[R];
     bool act[R];
@@ -1240,7 +1274,7 @@ __device__ __forceinline__ void tile_windows(const MainSmem& sm, int levels, int
         k[r] = 0.0f;
         act[r] = false;
         if (live[r] && sc[r] > 0.0f && iters > 0) {
-            const float kk = kA / (c * sc[r]);
+            const float kk = bisquare_k(kA, c, sc[r]);
             if (isfinite(kk)) {
                 k[r] = kk;
                 act[r] = true;
@@ -1338,13 +1372,13 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
             ssq = __builtin_fmaf(d, d, ssq);
         }
         ssq = group_sum<G>(ssq);
-        if (nplus > 0) sc = kScaleConst * __builtin_sqrtf(ssq / (float)nplus);
+        if (nplus > 0) sc = upper_scale(ssq, nplus);
     }
     // Phase 3 (Eqs. 2-4), as in the one-lane path
     float mu = m;
     const float kA = 0.5f * (1.0f + alpha);
     const float beta = (1.0f - alpha) / (1.0f + alpha);
-    const float kk = live && sc > 0.0f ? kA / (c * sc) : 0.0f;
+    const float kk = live && sc > 0.0f ? bisquare_k(kA, c, sc) : 0.0f;
     if (live && sc > 0.0f && iters > 0 && isfinite(kk)) {
         for (int it = 0; it < iters; ++it) {
             const float b = -mu * kk;
@@ -1353,7 +1387,7 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
             sw = group_sum<G>(sw);
             swv = group_sum<G>(swv);
             if (!(sw > 0.0f)) break;  // no weight left: keep mu
-            mu = mu + swv / (sw * kk);
+            mu = mu_update(mu, swv, sw, kk);
         }
     }
     if (p < t1 && l == 0) {
