@@ -131,17 +131,20 @@ def cpu_baseline(batch, budget_s: float = 15.0, first_curves: int | None = None,
     return out
 
 
-PROFILE = os.path.join(ROOT, "profiles", "umi_main_kernel__tess_batch_1000x18k_w361.md")
+WORKLOADS = {0: "tess_single_20k_w361", 1: "tess_batch_1000x18k_w361",
+             2: "kepler_ragged_2000x40k-70k_w25", 3: "mixed_ragged_10000x1k-120k_wmix"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2604_06602_amd", "csrc", f)
                   for f in ("umi_kernels.hip", "umi_internal.h")]
 
 
-def counted_traffic():
-    """HBM bytes per main-kernel launch from the committed counter summary,
-    or None when the kernel sources changed after those counters were taken."""
+def counted_traffic(workload):
+    """HBM bytes per main-kernel launch on `workload` from the committed
+    counter summary, or None when there is none or the kernel sources changed
+    after those counters were taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", "umi_main_kernel__%s.md" % WORKLOADS[workload])
     try:
-        text = open(PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -429,9 +432,7 @@ def main(argv=None):
         log("one curve: %.1f us device per call, %.1f us call to done (p50)"
             % (ms_step * 1e3, latency["call_to_done_us_p50"]))
 
-    wl = {0: "tess_single_20k_w361", 1: "tess_batch_1000x18k_w361",
-          2: "kepler_ragged_2000x40k-70k_w25",
-          3: "mixed_ragged_10000x1k-120k_wmix"}[args.workload]
+    wl = WORKLOADS[args.workload]
     out = {
         "metric": METRIC if args.workload == 1 else "window-estimates/s (%s)" % wl,
         "value": value,
@@ -452,7 +453,7 @@ def main(argv=None):
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "kernel": "umi_main_kernel",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(args.workload),
                      "target_frac": TARGET_FRAC,
                      "target_met": achieved / PEAK_FP32_TFLOPS >= TARGET_FRAC,
                      "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
@@ -466,8 +467,6 @@ def main(argv=None):
         out["comparison"] = per_curve
     if latency is not None:
         out["latency"] = latency
-    if args.workload != 1:
-        out["roofline"]["traffic"] = None  # the committed counters cover workload 1 only
     if not args.no_serve_leg:
         log("serving leg: 2000 curves/s for 3 s")
         del flux, tim, trend
