@@ -201,18 +201,25 @@ SERVE_POOL = 1000  # distinct curves drawn like the mixed workload, cycled by ar
 
 
 def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=50,
-                copy_threads=4):
+                copy_threads=4, scheduler="native"):
     """Open-loop serving: Poisson arrivals (rate curves/s) of curves drawn like
     the mixed workload, device-memory budget `budget_gb`; latency from the
-    scheduled arrival to the result in host memory."""
+    scheduled arrival to the result in host memory.  `scheduler`: "native"
+    (the library's serving loop) or "python" (the same loop in Python over the
+    library's plan and copy calls)."""
     import synth
-    from paper_2604_06602_amd.serve import BYTES_PER_SAMPLE, GpuExecutor, Server, run_open_loop
+    from paper_2604_06602_amd.serve import (BYTES_PER_SAMPLE, GpuExecutor, NativeServer, Server,
+                                            run_open_loop)
     log("drawing %d serving curves" % SERVE_POOL)
     pool = [synth.curve_for(4, i) for i in range(SERVE_POOL)]
     capacity = int(budget_gb * 1e9) // BYTES_PER_SAMPLE
     results = []
-    ex = GpuExecutor(capacity, max_curves=4096, max_W=721, copy_threads=copy_threads)
-    srv = Server(ex)
+    if scheduler == "native":
+        ex = None
+        srv = NativeServer(capacity, max_curves=4096, max_W=721, copy_threads=copy_threads)
+    else:
+        ex = GpuExecutor(capacity, max_curves=4096, max_W=721, copy_threads=copy_threads)
+        srv = Server(ex)
     for i in range(8):  # warm up: capture both graph slots, touch the pinned pool
         srv.submit(*pool[i]).result()
     for rate in rates:
@@ -223,7 +230,7 @@ def serve_sweep(rates, seconds, budget_gb, log, check_oracle=True, oracle_every=
             srv, pool, arrivals, keep,
             progress=lambda n, sec: log("rate %g/s: %d submitted after %.0f s" % (rate, n, sec)))
         entry = {"rate_curves_per_s": rate, "seconds": seconds, "requests": int(arrivals.size),
-                 "budget_gb": budget_gb, **summary}
+                 "budget_gb": budget_gb, "scheduler": scheduler, **summary}
         if check_oracle and kept:
             import oracle
             oracle.build(force=False)
@@ -286,6 +293,8 @@ def main(argv=None):
     ap.add_argument("--copy-threads", type=int, default=4,
                     help="host threads for pinned staging and result copies in serving")
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-scheduler", choices=["native", "python"], default="native",
+                    help="serving loop: the library's native scheduler, or the Python one")
     ap.add_argument("--no-serve-leg", action="store_true",
                     help="skip the short serving measurement of the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -319,7 +328,8 @@ def main(argv=None):
     if args.serve:
         rates = [float(r) for r in args.rates.split(",")]
         out = serve_sweep(rates, args.serve_seconds, args.budget_gb, log,
-                          check_oracle=not args.no_cpu_baseline, copy_threads=args.copy_threads)
+                          check_oracle=not args.no_cpu_baseline, copy_threads=args.copy_threads,
+                          scheduler=args.serve_scheduler)
         print(json.dumps(out), flush=True)
         return 0
 
@@ -472,8 +482,8 @@ def main(argv=None):
         del flux, tim, trend
         torch.cuda.empty_cache()
         # every 50th request is checked against the FP64 oracle after the run
-        out["serve"] = serve_sweep([2000.0], 3.0, args.budget_gb, log,
-                                   check_oracle=True)["rates"][0]
+        out["serve"] = serve_sweep([2000.0], 3.0, args.budget_gb, log, check_oracle=True,
+                                   scheduler=args.serve_scheduler)["rates"][0]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         if args.workload in (2, 3):

@@ -68,6 +68,97 @@ umi_status umi_host_copy_many(void* const* dst, const void* const* src, const in
 umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_t* bytes,
                           int64_t n, int32_t kind, void* stream);
 
+/*
+ * Native serving loop.  A server owns one device's resident arena (flux f32,
+ * time f64 and trend f32 arrays of `capacity` samples), a replayable plan over
+ * it, pinned staging rings, three streams (uploads, steps, downloads) and a
+ * scheduler thread.  Requests -- one light curve each, with its own W, alpha
+ * and c (Section 2; the Table 4 settings mix freely in one step) -- are
+ * admitted first-in first-out while their samples fit the arena (each
+ * admission group gets one contiguous range), staged into pinned memory and
+ * uploaded by the copy kernel, and run as continuous-batching steps: every
+ * uploaded group with the same iteration count joins the next step, up to
+ * max_curves curves and max_step_samples samples, with up to max_inflight
+ * steps on the device at once.  A finished step's trends are copied straight
+ * into each request's `out` buffer and the request is reported complete.
+ *
+ * umi_server_submit queues a request and returns at once.  flux [n] float32,
+ * time [n] float64 (or NULL: no gap breaks) and out [n] float32 are [host]
+ * memory the caller owns and keeps alive, unchanged (flux, time) and
+ * untouched (out), until the request is reported complete; `tag` is the
+ * caller's identifier, returned with the completion.  `arrival` is the
+ * request's arrival time in seconds of CLOCK_MONOTONIC (Python's
+ * time.perf_counter on Linux), or a negative value for "now"; latency
+ * figures run from it.  n = 0 completes at once.  Errors (nothing queued, no
+ * completion reported): W even, < 1 or > max_W, alpha or c not finite and
+ * > 0, iters < 0, n < 0 or n > capacity, a NULL flux or out with n > 0, or a
+ * server that is shutting down give UMI_ERR_INVALID_ARG.  Safe from any
+ * number of threads.
+ *
+ * umi_server_poll waits up to timeout_s seconds (0: no wait) for completions
+ * and moves at most `max` of them, oldest first, into out[], setting *n_out.
+ * A completion's status is UMI_OK when `out` holds the trend, else the error
+ * of the step the request ran in (its `out` is then unspecified).
+ *
+ * umi_server_shutdown finishes every queued request, stops the scheduler and
+ * frees the device and pinned memory; completions stay available to
+ * umi_server_poll.  umi_server_destroy shuts down (if not done yet) and frees
+ * the server.  umi_server_stats fills *out with counters since creation or
+ * the last umi_server_reset_stats.
+ *
+ * Errors of umi_server_create: a config field out of range gives
+ * UMI_ERR_INVALID_ARG; device or pinned memory that cannot be allocated gives
+ * UMI_ERR_NO_MEMORY; a runtime error UMI_ERR_DEVICE.  A failure inside the
+ * scheduler thread fails every unresolved request with UMI_ERR_DEVICE and
+ * stops it; later submits give UMI_ERR_INVALID_ARG.
+ */
+typedef struct umi_server umi_server;
+
+typedef struct {
+    int64_t capacity;         /* arena samples (> 0) */
+    int64_t max_step_samples; /* samples per step and admission group (0: 2^25); a
+                                 lone larger request runs as a step of its own */
+    int64_t staging_bytes;    /* pinned upload ring (0: 4 GiB); the download ring
+                                 is a third of it */
+    int32_t max_curves;       /* curves per step (0: 4096) */
+    int32_t max_W;            /* largest W of any request (0: 721) */
+    int32_t max_inflight;     /* steps on the device at once (0: 2) */
+    int32_t copy_threads;     /* threads of the staging copies (0: 4) */
+    int32_t device;           /* HIP device */
+    int32_t reserved;         /* must be 0 */
+} umi_server_config;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;           /* umi_status */
+    int32_t reserved;
+    double admitted;          /* CLOCK_MONOTONIC seconds: range allocated */
+    double launched;          /* its step enqueued */
+    double done;              /* result in `out` */
+} umi_server_completion;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected;
+    int64_t steps, step_curves, samples, largest_step_samples;
+    int64_t arena_capacity, arena_used, arena_high_water;
+    int64_t staging_fallbacks;  /* one-off pinned blocks for oversize groups */
+    double loop_s[4];           /* scheduler time: finish, admit, upload, launch */
+    double longest_iteration_s;
+    double longest_iteration_loop_s[4];
+    double exec_s[4];           /* staging copy, upload enqueue, plan run, result copy */
+} umi_server_stats;
+
+umi_status umi_server_create(const umi_server_config* config, umi_server** out);
+umi_status umi_server_submit(umi_server* server, const float* flux, const double* time,
+                             int64_t n, int32_t W, float alpha, float c, int32_t iters,
+                             double arrival, float* out, uint64_t tag);
+umi_status umi_server_poll(umi_server* server, umi_server_completion* out, int32_t max,
+                           double timeout_s, int32_t* n_out);
+umi_status umi_server_stats_get(umi_server* server, umi_server_stats* out);
+umi_status umi_server_reset_stats(umi_server* server);
+umi_status umi_server_shutdown(umi_server* server);
+umi_status umi_server_destroy(umi_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,29 @@ class Options(ctypes.Structure):
                 ("window_days", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int64), ("max_step_samples", ctypes.c_int64),
+                ("staging_bytes", ctypes.c_int64), ("max_curves", ctypes.c_int32),
+                ("max_W", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("copy_threads", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ServerCompletion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("admitted", ctypes.c_double), ("launched", ctypes.c_double),
+                ("done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "completed", "failed", "rejected", "steps", "step_curves", "samples",
+        "largest_step_samples", "arena_capacity", "arena_used", "arena_high_water",
+        "staging_fallbacks")] + [
+        ("loop_s", ctypes.c_double * 4), ("longest_iteration_s", ctypes.c_double),
+        ("longest_iteration_loop_s", ctypes.c_double * 4), ("exec_s", ctypes.c_double * 4)]
+
+
 _vp = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -112,6 +135,20 @@ def _load():
     lib.umi_host_copy_many.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32]
     lib.umi_copy_async.restype = ctypes.c_int
     lib.umi_copy_async.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
+    lib.umi_server_create.restype = ctypes.c_int
+    lib.umi_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
+    lib.umi_server_submit.restype = ctypes.c_int
+    lib.umi_server_submit.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                      ctypes.c_double, _vp, ctypes.c_uint64]
+    lib.umi_server_poll.restype = ctypes.c_int
+    lib.umi_server_poll.argtypes = [_vp, ctypes.POINTER(ServerCompletion), ctypes.c_int32,
+                                    ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
+    lib.umi_server_stats_get.restype = ctypes.c_int
+    lib.umi_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    for name in ("umi_server_reset_stats", "umi_server_shutdown", "umi_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = [_vp]
     return lib
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libumi.so")
-SOURCES = ["umi_kernels.hip", "umi_host.hip"]
+SOURCES = ["umi_kernels.hip", "umi_host.hip", "umi_server.hip"]
 DIAG_PATH = os.path.join(HERE, "libumi_diag.so")   # measurement aid (FMA throughput)
 DIAG_SOURCES = ["umi_diag.hip"]
 ARCH = "gfx950"

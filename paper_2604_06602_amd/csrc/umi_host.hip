@@ -1,7 +1,8 @@
 // Host side of the UMI C ABI (include/umi.h): argument checks, the batch
 // packer (cost-sorted curve table), per-(device, stream) workspaces, the
 // tuning table, the kernel launches, replayable plans (hipGraph), and the
-// serving loop's batched host copies (include/umi_serve.h).
+// serving loop's batched host copies (include/umi_serve.h; the serving loop
+// itself is in umi_server.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,8 +26,8 @@
 
 namespace umi {
 
-hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
+hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
+                          const uint8_t* stage, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
                           hipStream_t stream);
 hipError_t launch_copy(const CopyBatch& cb, hipStream_t stream);
@@ -453,22 +454,27 @@ PrepLaunch prep_launch_for(int64_t ncurves, int64_t nchunks, int n_cu)
 }
 
 // Enqueue the pre-pass and estimate kernels for a staged block (header +
-// curve table, at `dblock` on the device by the time the stream reaches them).
-// In per-curve mode `table` and `curve_tiles` (host copies of the staged
-// table, `ncurves` entries) give each curve's tile range and length.
+// curve table).  With `stage` (the device address of the pinned host block
+// holding it) the pre-pass reads the block there and copies it to `dblock`
+// for the estimate kernel; without, the block is at `dblock` on the device by
+// the time the stream reaches the kernels (per-curve mode always).  In
+// per-curve mode `table` and `curve_tiles` (host copies of the staged table,
+// `ncurves` entries) give each curve's tile range and length.  `staged`, if
+// given, is recorded once the pre-pass is done with the staging block.
 hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, float* median,
-                           const uint8_t* dblock, const DeviceBuffers& b, int mode,
+                           uint8_t* dblock, const uint8_t* stage, const DeviceBuffers& b, int mode,
                            const CurveDesc* table, const int64_t* curve_tiles, int ncurves,
                            PrepLaunch prep, int main_grid, int feat, hipEvent_t ev0,
-                           hipEvent_t ev1, hipStream_t stream)
+                           hipEvent_t ev1, hipEvent_t staged, hipStream_t stream)
 {
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblock);
     const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
     hipError_t e;
     if (mode == UMI_MODE_PERSISTENT) {
-        if ((e = launch_prepass(flux, time, hdr, curves, -1, prep.grid, b.segid, b.tiles, b.ctr,
+        if ((e = launch_prepass(flux, time, dblock, stage, -1, prep.grid, b.segid, b.tiles, b.ctr,
                                 b.recs, true, prep.walk, stream)) != hipSuccess)
             return e;
+        if (staged && (e = hipEventRecord(staged, stream)) != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, 0, -1, &b.ctr->queue, main_grid,
                              trend, median, feat, stream)) != hipSuccess)
@@ -480,8 +486,8 @@ hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, 
     // curve, one workgroup per tile
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     for (int i = 0; i < ncurves; ++i) {
-        if ((e = launch_prepass(flux, time, hdr, curves, i, 1, b.segid, b.tiles, b.ctr, b.recs,
-                                false, true, stream)) != hipSuccess)
+        if ((e = launch_prepass(flux, time, dblock, nullptr, i, 1, b.segid, b.tiles, b.ctr,
+                                b.recs, false, true, stream)) != hipSuccess)
             return e;
         const int nt = (int)curve_tiles[i];
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, table[i].tile_base, nt, nullptr,
@@ -503,6 +509,7 @@ struct Workspace {
     uint8_t* dblock = nullptr;   // header + curve table on the device
     int64_t cap_dblock = 0;
     uint8_t* hblock = nullptr;   // pinned staging for it
+    uint8_t* hblock_dev = nullptr;  // hblock's device address
     int64_t cap_hblock = 0;
     hipEvent_t staged = nullptr; // last copy out of hblock
     bool staged_pending = false;
@@ -513,7 +520,7 @@ struct Workspace {
         if (dblock) (void)hipFree(dblock);
         if (hblock) (void)hipHostFree(hblock);
         if (staged) (void)hipEventDestroy(staged);
-        dblock = hblock = nullptr;
+        dblock = hblock = hblock_dev = nullptr;
         cap_dblock = cap_hblock = 0;
         staged = nullptr;
         staged_pending = false;
@@ -534,12 +541,14 @@ struct Workspace {
         if ((e = grow(&dblock, &cap_dblock, bytes)) != hipSuccess) return e;
         if (bytes > cap_hblock) {
             if (hblock) (void)hipHostFree(hblock);
-            hblock = nullptr;
+            hblock = hblock_dev = nullptr;
             cap_hblock = 0;
             const int64_t n = std::max<int64_t>(bytes + bytes / 4, 4096);
             e = hipHostMalloc(reinterpret_cast<void**>(&hblock), (size_t)n, hipHostMallocDefault);
             if (e != hipSuccess) return e;
             cap_hblock = n;
+            e = hipHostGetDevicePointer(reinterpret_cast<void**>(&hblock_dev), hblock, 0);
+            if (e != hipSuccess) return e;
         }
         if (!staged) e = hipEventCreateWithFlags(&staged, hipEventDisableTiming);
         return e;
@@ -577,6 +586,10 @@ int cu_count(int device)
 }
 
 }  // namespace
+
+// Sets the calling thread's umi_last_error text (for the other host sources
+// of the library) and returns `s`.
+umi_status report_error(umi_status s, const std::string& msg) { return fail(s, msg); }
 
 // ---------------------------------------------------------------------------
 // direct calls: curves at explicit offsets
@@ -616,23 +629,29 @@ umi_status detrend_gather(const float* flux, const double* time, const int64_t* 
     std::lock_guard<std::mutex> lk(ws->mu);
     if ((e = ws->reserve(span, nc, p.ntiles, p.nchunks)) != hipSuccess)
         return fail_hip(e, "workspace allocation");
-    if (ws->staged_pending) {  // the previous copy out of the staging block must be done
+    if (ws->staged_pending) {  // the previous reads of the staging block must be done
         if ((e = hipEventSynchronize(ws->staged)) != hipSuccess)
             return fail_hip(e, "hipEventSynchronize");
         ws->staged_pending = false;
     }
     write_block(ws->hblock, p.curves.data(), nc, p.ntiles, p.nchunks, iters, o, time);
-    if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return fail_hip(e, "curve table copy");
-    if ((e = hipEventRecord(ws->staged, stream)) != hipSuccess)
-        return fail_hip(e, "hipEventRecord");
+    // a persistent launch's pre-pass reads the block from pinned memory and
+    // copies it to the device itself; per-curve launches take a copy first
+    const bool direct = opt.mode == UMI_MODE_PERSISTENT;
+    if (!direct) {
+        if ((e = hipMemcpyAsync(ws->dblock, ws->hblock, block_bytes(nc), hipMemcpyHostToDevice,
+                                stream)) != hipSuccess)
+            return fail_hip(e, "curve table copy");
+        if ((e = hipEventRecord(ws->staged, stream)) != hipSuccess)
+            return fail_hip(e, "hipEventRecord");
+    }
     ws->staged_pending = true;
     const int grid = (int)std::min<int64_t>(p.ntiles, (int64_t)p.gpc * cu_count(device));
-    e = enqueue_kernels(flux, time, trend, median, ws->dblock, ws->buf, opt.mode, p.curves.data(),
-                        p.curve_tiles.data(), (int)nc,
+    e = enqueue_kernels(flux, time, trend, median, ws->dblock, direct ? ws->hblock_dev : nullptr,
+                        ws->buf, opt.mode, p.curves.data(), p.curve_tiles.data(), (int)nc,
                         prep_launch_for(nc, p.nchunks, cu_count(device)), grid, p.feat,
-                        (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, stream);
+                        (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop,
+                        direct ? ws->staged : nullptr, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -755,10 +774,12 @@ struct umi_plan {
     umi::DeviceBuffers buf;
     // Two captured graphs per slot: [0] for batches of at most
     // kPrepSmallChunks pre-pass chunks (the chunked pre-pass over that many
-    // workgroups, and a copy of that much of the table), [1] for any batch
-    // (the curve walker over max_curves workgroups).
+    // workgroups), [1] for any batch (the curve walker over max_curves
+    // workgroups).  Either pre-pass reads the slot's pinned block and copies
+    // it to the slot's device block for the estimate kernel.
     struct Slot {
         uint8_t* host = nullptr;    // pinned header + curve table
+        uint8_t* host_dev = nullptr;  // its device address
         uint8_t* dev = nullptr;     // its device copy
         hipGraph_t graph[2] = {nullptr, nullptr};
         hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -802,20 +823,18 @@ umi::PrepLaunch plan_kind_prep(const umi_plan* p, int kind)
                      : umi::PrepLaunch{true, (int)p->max_curves};
 }
 
-// Capture slot `si`'s graph of `kind`: the copy of the staged block, the
-// pre-pass and the persistent estimate kernel.  Nothing runs during capture.
+// Capture slot `si`'s graph of `kind`: the pre-pass (which reads the staged
+// block from pinned memory and copies it to the device) and the persistent
+// estimate kernel.  Nothing runs during capture.
 hipError_t plan_capture(umi_plan* p, int si, int kind)
 {
     umi_plan::Slot& s = p->slot[si];
     hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t ce = hipMemcpyAsync(s.dev, s.host, umi::block_bytes(plan_kind_curves(p, kind)),
-                                   hipMemcpyHostToDevice, p->stream);
-    if (ce == hipSuccess)
-        ce = umi::enqueue_kernels(p->flux, p->time, p->trend, p->median, s.dev, p->buf,
-                                  UMI_MODE_PERSISTENT, nullptr, nullptr,
-                                  (int)plan_kind_curves(p, kind), plan_kind_prep(p, kind),
-                                  p->main_grid, umi::kFeatAll, nullptr, nullptr, p->stream);
+    const hipError_t ce = umi::enqueue_kernels(
+        p->flux, p->time, p->trend, p->median, s.dev, s.host_dev, p->buf, UMI_MODE_PERSISTENT,
+        nullptr, nullptr, (int)plan_kind_curves(p, kind), plan_kind_prep(p, kind), p->main_grid,
+        umi::kFeatAll, nullptr, nullptr, nullptr, p->stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p->stream, &g);
     if (ce != hipSuccess || e != hipSuccess) {
@@ -963,10 +982,10 @@ umi_status detrend_batch(const float* flux, const double* time, const int64_t* l
     b.recs = reinterpret_cast<ChunkRec*>(base + kRecsOff);
     b.cap_recs = kMaxChunks;
     const int grid = (int)std::min<int64_t>(v.ntiles, (int64_t)v.gpc * n_cu);
-    e = enqueue_kernels(flux, time, trend, median, base + kBlockOff, b, opt.mode, g_curves,
-                        g_curve_tiles, (int)v.ncurves, prep_launch_for(v.ncurves, v.nchunks, n_cu),
-                        grid, v.feat, (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop,
-                        stream);
+    e = enqueue_kernels(flux, time, trend, median, base + kBlockOff, nullptr, b, opt.mode,
+                        g_curves, g_curve_tiles, (int)v.ncurves,
+                        prep_launch_for(v.ncurves, v.nchunks, n_cu), grid, v.feat,
+                        (hipEvent_t)opt.main_start, (hipEvent_t)opt.main_stop, nullptr, stream);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return UMI_OK;
 }
@@ -1110,6 +1129,8 @@ umi_status umi_plan_create(umi_plan** out, int64_t capacity, int64_t max_curves,
     for (auto& s : p->slot) {
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&s.host), bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s.host_dev), s.host, 0);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s.dev), bytes);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e == hipSuccess) std::memset(s.host, 0, bytes);

@@ -280,13 +280,33 @@ __device__ SegState lookback(const ChunkRec* __restrict__ recs, int g, int g0, u
     return acc;
 }
 
+// The batch header and curve table the pre-pass reads sit either in device
+// memory already or in the caller's pinned staging block, which the device
+// reads over the bus; in the latter case the pre-pass also copies the block
+// into device memory (`to`) for the estimate kernel, spread over the grid in
+// 8-byte words, so no separate copy precedes it.
+__device__ __forceinline__ void stage_block_copy(const uint8_t* __restrict__ src,
+                                                 uint8_t* __restrict__ to, int n_curves, int nt)
+{
+    if (to == nullptr) return;
+    const int words = (int)((sizeof(BatchHeader) + (size_t)n_curves * sizeof(CurveDesc)) / 8);
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
+    uint64_t* d = reinterpret_cast<uint64_t*>(to);
+    for (int i = (int)(blockIdx.x * nt + threadIdx.x); i < words; i += (int)gridDim.x * nt)
+        d[i] = s[i];
+}
+static_assert(sizeof(BatchHeader) % 8 == 0 && sizeof(CurveDesc) % 8 == 0, "8-byte words");
+
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
-    const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_one,
+    const uint8_t* __restrict__ block, uint8_t* __restrict__ block_to, int curve_one,
     int32_t* __restrict__ segid, int2* __restrict__ tiles, Counters* __restrict__ ctr,
     ChunkRec* __restrict__ recs, int clear_queue)
 {
+    const BatchHeader* __restrict__ hdr = reinterpret_cast<const BatchHeader*>(block);
+    const CurveDesc* __restrict__ curves =
+        reinterpret_cast<const CurveDesc*>(block + sizeof(BatchHeader));
     constexpr int NW = NT / 64;
     constexpr int kChunk = NT * K;
     __shared__ int sh_vi[NW];      // per wave: latest valid index
@@ -311,6 +331,7 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
                              ? (curves[curve_one].len + kChunk - 1) / kChunk
                              : hdr->n_chunks;
     const int n_curves = hdr->n_curves;
+    stage_block_copy(block, block_to, n_curves, NT);
 
     for (;;) {
         if (tid == 0) sh_ticket = (int)atomicAdd(&ctr->tickets, 1u);
@@ -549,9 +570,12 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
-    const BatchHeader* __restrict__ hdr, const CurveDesc* __restrict__ curves, int curve_first,
+    const uint8_t* __restrict__ block, uint8_t* __restrict__ block_to, int curve_first,
     int32_t* __restrict__ segid, int2* __restrict__ tiles, uint32_t* __restrict__ counter)
 {
+    const BatchHeader* __restrict__ hdr = reinterpret_cast<const BatchHeader*>(block);
+    const CurveDesc* __restrict__ curves =
+        reinterpret_cast<const CurveDesc*>(block + sizeof(BatchHeader));
     constexpr int NW = NT / 64;
     __shared__ int sh_vi[NW];      // per wave: latest valid index
     __shared__ double sh_vt[NW];   //           its time
@@ -560,8 +584,10 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
     __shared__ int sh_sz[NW];      //           valid samples before it
 
     if (counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    const int n_curves = hdr->n_curves;
+    stage_block_copy(block, block_to, n_curves, NT);
     const int cidx = curve_first + (int)blockIdx.x;
-    if (cidx >= hdr->n_curves) return;  // fixed-size grids cover fewer curves
+    if (cidx >= n_curves) return;  // fixed-size grids cover fewer curves
     const CurveDesc cd = curves[cidx];
 
     const int ntiles = cd.len > 0 ? (cd.len + cd.tile - 1) / cd.tile : 0;
@@ -1343,6 +1369,23 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
+// f(x[j]) for j = l, l + G, l + 2G, ... below n, in that order; eight loads
+// are issued ahead of their use, so a lane waits on LDS once per eight
+// samples rather than once per sample (the order of the sums is unchanged).
+template <int G, class F>
+__device__ __forceinline__ void strided_sweep(const float* __restrict__ x, int l, int n, F&& f)
+{
+    int j = l;
+    for (; j + 7 * G < n; j += 8 * G) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = x[j + u * G];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f(v[u]);
+    }
+    for (; j < n; j += G) f(x[j]);
+}
+
 template <int G, int kFeat>
 __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int levels, int nv,
                                                    const CurveDesc& cd, int h, int s0, int N,
@@ -1367,10 +1410,10 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
     if (live && scale != UMI_SCALE_MAD) {
         // Phase 2 (Eq. 1)
         float ssq = 0.0f;
-        for (int j = l; j < (int)n; j += G) {
-            const float d = __builtin_fmaxf(x[j] - m, 0.0f);
+        strided_sweep<G>(x, l, (int)n, [&](float xj) {
+            const float d = __builtin_fmaxf(xj - m, 0.0f);
             ssq = __builtin_fmaf(d, d, ssq);
-        }
+        });
         ssq = group_sum<G>(ssq);
         if (nplus > 0) sc = upper_scale(ssq, nplus);
     }
@@ -1383,7 +1426,8 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
         for (int it = 0; it < iters; ++it) {
             const float b = -mu * kk;
             float sw = 0.0f, swv = 0.0f;
-            for (int j = l; j < (int)n; j += G) bisquare_acc(x[j], kk, b, beta, sw, swv);
+            strided_sweep<G>(x, l, (int)n,
+                             [&](float xj) { bisquare_acc(xj, kk, b, beta, sw, swv); });
             sw = group_sum<G>(sw);
             swv = group_sum<G>(swv);
             if (!(sw > 0.0f)) break;  // no weight left: keep mu
@@ -1652,20 +1696,24 @@ __global__ __launch_bounds__(256) void umi_copy_kernel(CopyBatch cb)
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers (the host library calls only these).
 
-hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
+hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
+                          const uint8_t* stage, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
                           hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
+    // read the header and table from the staging block (and copy them into
+    // `block`), or from `block` itself
+    const uint8_t* src = stage ? stage : block;
+    uint8_t* to = stage ? block : nullptr;
     if (walk)  // one workgroup per curve, from curve_one (or the first) on
         hipLaunchKernelGGL((umi_prepass_walk_kernel<kPrepThreads, kPrepWalkItems>), dim3(grid),
-                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves,
+                           dim3(kPrepThreads), 0, stream, flux, time, src, to,
                            curve_one < 0 ? 0 : curve_one, segid, tiles,
                            clear_queue ? &ctr->queue : nullptr);
     else
         hipLaunchKernelGGL((umi_prepass_chunk_kernel<kPrepThreads, kPrepItems>), dim3(grid),
-                           dim3(kPrepThreads), 0, stream, flux, time, hdr, curves, curve_one,
+                           dim3(kPrepThreads), 0, stream, flux, time, src, to, curve_one,
                            segid, tiles, ctr, recs, clear_queue ? 1 : 0);
     return hipGetLastError();
 }

@@ -800,6 +800,183 @@ class Server:
 
 
 # ---------------------------------------------------------------------------
+# native server
+
+
+class NativeServer:
+    """The library's native serving loop (include/umi_serve.h, umi_server_*)
+    behind the same interface as ``Server``: ``submit`` returns a Future,
+    ``close``, ``summary`` and ``reset_stats``.  Admission, staging, uploads,
+    steps and the copies of results into each request's output run in the
+    library's own threads; Python validates a request, keeps its arrays alive
+    until it completes, and resolves futures from one completion thread.
+
+    The arena holds ``capacity`` samples (BYTES_PER_SAMPLE of device memory
+    each, with the plan workspace).  Times are Python's perf_counter clock,
+    which is the clock the library stamps completions with (CLOCK_MONOTONIC)."""
+
+    MAX_STEP_SAMPLES = Server.MAX_STEP_SAMPLES
+
+    def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device: int = 0,
+                 max_step_samples: int | None = None, max_inflight: int = 2,
+                 staging_bytes: int = 4 << 30, copy_threads: int = 4):
+        import ctypes
+
+        from . import _lib
+        self._lib = _lib
+        self._ct = ctypes
+        self.capacity = int(capacity)
+        self.max_W = int(max_W)
+        self.clock = _time.perf_counter
+        cfg = _lib.ServerConfig(self.capacity, int(max_step_samples or self.MAX_STEP_SAMPLES),
+                                int(staging_bytes), int(max_curves), self.max_W,
+                                int(max_inflight), int(copy_threads), int(device), 0)
+        h = ctypes.c_void_p()
+        _lib._check(_lib.lib.umi_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._lock = threading.Lock()
+        self._pending: dict = {}  # tag -> (future, flux, time, out, arrival)
+        self._tags = itertools.count()
+        self.stats = Stats()
+        self._stop = False
+        self._closed = False
+        self._poller = threading.Thread(target=self._poll_loop, name="umi-serve-native",
+                                        daemon=True)
+        self._poller.start()
+
+    def submit(self, flux, time=None, W: int = 361, alpha: float = 2.0, c: float = 5.0,
+               iters: int = 5, arrival: float | None = None) -> Future:
+        fut: Future = Future()
+        flux = np.ascontiguousarray(flux, dtype=np.float32)
+        time_ = None if time is None else np.ascontiguousarray(time, dtype=np.float64)
+        arrival = self.clock() if arrival is None else float(arrival)
+        try:
+            if flux.ndim != 1 or (time_ is not None and time_.shape != flux.shape):
+                raise ValueError("flux and time must be 1-D of equal length")
+            if W < 1 or W % 2 == 0 or W > self.max_W:
+                raise ValueError("W must be odd, 1 <= W <= %d" % self.max_W)
+            with np.errstate(over="ignore"):
+                a32, c32 = np.float32(alpha), np.float32(c)
+            if not (np.isfinite(a32) and a32 > 0 and np.isfinite(c32) and c32 > 0):
+                raise ValueError("alpha and c must be finite and > 0 as float32")
+            if int(iters) != iters or iters < 0:
+                raise ValueError("iters must be an integer >= 0")
+            if flux.size > self.capacity:
+                raise Rejected("curve of %d samples exceeds the device budget of %d samples"
+                               % (flux.size, self.capacity))
+        except ValueError as e:
+            with self._lock:
+                self.stats.rejected += 1
+            fut.set_exception(e)
+            return fut
+        if flux.size == 0:
+            fut.set_result(np.zeros(0, np.float32))
+            return fut
+        out = np.empty(flux.size, np.float32)
+        tag = next(self._tags)
+        with self._lock:
+            if self._closed:
+                raise RuntimeError("server is closed")
+            self._pending[tag] = (fut, flux, time_, out, arrival)
+            st = self.stats
+            st.submit_lag.append(self.clock() - arrival)
+            if st.first_arrival is None or arrival < st.first_arrival:
+                st.first_arrival = arrival
+        status = self._lib.lib.umi_server_submit(
+            self._h, flux.ctypes.data, None if time_ is None else time_.ctypes.data, flux.size,
+            int(W), float(a32), float(c32), int(iters), arrival, out.ctypes.data, tag)
+        if status != self._lib.UMI_OK:
+            with self._lock:
+                self._pending.pop(tag, None)
+            raise self._lib.UmiError(status, self._lib.last_error())
+        return fut
+
+    def _poll_loop(self):
+        ct = self._ct
+        lib = self._lib.lib
+        buf = (self._lib.ServerCompletion * 512)()
+        n = ct.c_int32(0)
+        while True:
+            lib.umi_server_poll(self._h, buf, 512, 0.05, ct.byref(n))
+            k = n.value
+            if k == 0:
+                if self._stop:
+                    return
+                continue
+            settle = []
+            with self._lock:
+                st = self.stats
+                for j in range(k):
+                    cpl = buf[j]
+                    fut, flux, _, out, arrival = self._pending.pop(cpl.tag)
+                    if cpl.status == 0:
+                        st.completed += 1
+                        st.samples += flux.size
+                        st.latencies.append(cpl.done - arrival)
+                        st.queued.append(cpl.admitted - arrival)
+                        st.staged.append(cpl.launched - cpl.admitted)
+                        st.service.append(cpl.done - cpl.launched)
+                        if st.last_done is None or cpl.done > st.last_done:
+                            st.last_done = cpl.done
+                        settle.append((fut, out, None))
+                    else:
+                        st.failed += 1
+                        settle.append((fut, None, self._lib.UmiError(
+                            cpl.status, "the step this request ran in failed")))
+            for fut, out, err in settle:  # statistics are complete before any caller wakes
+                if fut.cancelled():
+                    continue
+                if err is None:
+                    fut.set_result(out)
+                else:
+                    fut.set_exception(err)
+
+    def close(self, timeout: float | None = None):
+        """Finish everything submitted, then stop and free the server."""
+        with self._lock:
+            if self._closed:
+                return
+            self._closed = True
+        self._lib.lib.umi_server_shutdown(self._h)
+        self._stop = True
+        self._poller.join(timeout)
+        self._lib.lib.umi_server_destroy(self._h)
+        self._h = None
+
+    def native_stats(self) -> dict:
+        ns = self._lib.ServerStats()
+        self._lib._check(self._lib.lib.umi_server_stats_get(self._h, self._ct.byref(ns)))
+        return {name: (list(getattr(ns, name)) if name.endswith("_s") and name != "longest_iteration_s"
+                       else getattr(ns, name)) for name, _ in ns._fields_}
+
+    def summary(self) -> dict:
+        ns = self.native_stats()
+        with self._lock:
+            out = self.stats.summary()
+        phases = ("finish", "admit", "upload", "launch")
+        out["steps"] = ns["steps"]
+        out["mean_curves_per_step"] = ns["step_curves"] / ns["steps"] if ns["steps"] else None
+        out["largest_step_samples"] = ns["largest_step_samples"]
+        out["scheduler_phase_s"] = dict(zip(phases, ns["loop_s"]))
+        out["scheduler_longest_iteration_ms"] = ns["longest_iteration_s"] * 1e3
+        out["scheduler_longest_iteration_phases_ms"] = {
+            k: v * 1e3 for k, v in zip(phases, ns["longest_iteration_loop_s"])}
+        out["executor_phase_s"] = dict(zip(("stage_copy", "upload_enqueue", "launch_plan",
+                                            "results"), ns["exec_s"]))
+        out["arena_high_water_samples"] = ns["arena_high_water"]
+        out["arena_capacity_samples"] = ns["arena_capacity"]
+        out["pinned_fallbacks"] = ns["staging_fallbacks"]
+        out["scheduler"] = "native"
+        return out
+
+    def reset_stats(self):
+        """Start a new measurement window (e.g. after a warm-up)."""
+        with self._lock:
+            self.stats = Stats()
+        self._lib._check(self._lib.lib.umi_server_reset_stats(self._h))
+
+
+# ---------------------------------------------------------------------------
 # open-loop driver
 
 

@@ -9,19 +9,25 @@
 // anything, or an offset outside the caller's arrays, is an out-of-bounds
 // access the sanitizer reports.  Exercised: argument checks, the tuning
 // table, direct batches (packed and gathered, with options and explicit
-// launches), plans (create / run / destroy, both graph kinds), the
-// allocation-free batch call, the host copy pool from several threads at
-// once, and umi_release.  Prints "host checks ok" and exits 0 on success.
-// An optional argument sets the number of random batches per pass.
+// launches), plans (create / run / destroy, both graph kinds, whose captured
+// launches the stand-in replays), the allocation-free batch call, the host
+// copy pool from several threads at once, the native serving loop (requests
+// from several threads, oversize requests, a failing step), and
+// umi_release.  The stand-in estimate kernel writes flux + W at every output
+// position, so results show that each curve's samples and window reached
+// the right place.  Prints "host checks ok" and exits 0 on success.  An
+// optional argument sets the number of random batches per pass.
 #include "umi_host.hip"
+#include "umi_server.hip"
 
 #include <random>
 #include <thread>
 
 namespace {
 
-int g_failures = 0;
-long g_prepass = 0, g_main = 0;
+std::atomic<int> g_failures{0};
+std::atomic<long> g_prepass{0}, g_main{0};
+std::atomic<int> g_fail_W{0};  // the estimate kernel fails for curves of this W
 
 #define CHECK(cond)                                                               \
     do {                                                                          \
@@ -40,12 +46,20 @@ namespace umi {
 // every chunk reads its flux and time, writes its segment words, its chunk
 // record and the tiles that start in it (what the kernel writes), and the
 // counters come back to zero with the launch count advanced.
-hipError_t launch_prepass(const float* flux, const double* time, const BatchHeader* hdr,
-                          const CurveDesc* curves, int curve_one, int grid, int32_t* segid,
-                          int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
-                          hipStream_t)
+hipError_t prepass_now(const float* flux, const double* time, uint8_t* block,
+                       const uint8_t* stage, int curve_one, int grid, int32_t* segid,
+                       int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk)
 {
     ++g_prepass;
+    // with a staging block, the header and table come from there and are
+    // copied to the device block (what the kernels do)
+    if (stage) {
+        const int nc = reinterpret_cast<const BatchHeader*>(stage)->n_curves;
+        CHECK(nc >= 0);
+        std::memcpy(block, stage, sizeof(BatchHeader) + (size_t)nc * sizeof(CurveDesc));
+    }
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(block);
+    const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(block + sizeof(BatchHeader));
     CHECK(grid >= 1);
     if (walk && curve_one < 0) CHECK(grid >= hdr->n_curves);  // a workgroup per curve
     if (walk && curve_one >= 0) CHECK(grid == 1);
@@ -99,24 +113,38 @@ hipError_t launch_prepass(const float* flux, const double* time, const BatchHead
     return hipSuccess;
 }
 
+hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
+                          const uint8_t* stage, int curve_one, int grid, int32_t* segid,
+                          int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
+                          hipStream_t)
+{
+    if (curve_one >= 0) CHECK(stage == nullptr);  // per-curve launches copy the block first
+    return fake_hip::record_or_run([=] {
+        return prepass_now(flux, time, block, stage, curve_one, grid, segid, tiles, ctr, recs,
+                           clear_queue, walk);
+    });
+}
+
 // The copy kernel: each copy of the list is done in full, and the pieces
 // count matches the sizes.
 hipError_t launch_copy(const CopyBatch& cb, hipStream_t)
 {
-    CHECK(cb.n >= 1 && cb.n <= kCopyMax);
-    for (int i = 0; i < cb.n; ++i) {
-        CHECK(cb.first[i + 1] - cb.first[i] == (cb.bytes[i] + kCopyPieceBytes - 1) / kCopyPieceBytes);
-        std::memcpy(cb.dst[i], cb.src[i], (size_t)cb.bytes[i]);
-    }
-    return hipSuccess;
+    return fake_hip::record_or_run([cb] {
+        CHECK(cb.n >= 1 && cb.n <= kCopyMax);
+        for (int i = 0; i < cb.n; ++i) {
+            CHECK(cb.first[i + 1] - cb.first[i] ==
+                  (cb.bytes[i] + kCopyPieceBytes - 1) / kCopyPieceBytes);
+            std::memcpy(cb.dst[i], cb.src[i], (size_t)cb.bytes[i]);
+        }
+        return hipSuccess;
+    });
 }
 
 // The estimate kernel: every tile of its range lies in its curve, its
 // staged span fits the workgroup, and the outputs of its positions exist.
-hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
-                       const CurveDesc* curves, const int2* tiles, int tile_first,
-                       int tile_count, uint32_t* counter, int grid, float* trend, float* median,
-                       int feat, hipStream_t)
+hipError_t main_now(const float* flux, const int32_t* segid, const BatchHeader* hdr,
+                    const CurveDesc* curves, const int2* tiles, int tile_first, int tile_count,
+                    uint32_t* counter, int grid, float* trend, float* median, int feat)
 {
     ++g_main;
     CHECK(grid >= 1);
@@ -138,14 +166,26 @@ hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeade
         if (!(feat & kFeatExtra)) CHECK(cd.window_days == 0.0 && hdr->scale == UMI_SCALE_UPPER_RMS);
         CHECK(split_lanes(cd.tile) * std::min(cd.tile, kMainThreads) <= kMainThreads ||
               split_lanes(cd.tile) == 1);
+        if (cd.W == g_fail_W.load()) return hipErrorLaunchFailure;
         volatile float fs = 0.0f;
         for (int i = s0; i < s1; ++i) fs = fs + flux[cd.off + i] + (float)segid[cd.off + i];
         for (int p = t0; p < t1; ++p) {
-            trend[cd.off + p] = 1.0f;
+            trend[cd.off + p] = flux[cd.off + p] + (float)cd.W;
             if (median) median[cd.off + p] = 1.0f;
         }
     }
     return hipSuccess;
+}
+
+hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
+                       const CurveDesc* curves, const int2* tiles, int tile_first,
+                       int tile_count, uint32_t* counter, int grid, float* trend, float* median,
+                       int feat, hipStream_t)
+{
+    return fake_hip::record_or_run([=] {
+        return main_now(flux, segid, hdr, curves, tiles, tile_first, tile_count, counter, grid,
+                        trend, median, feat);
+    });
 }
 
 }  // namespace umi
@@ -279,6 +319,12 @@ void check_plans()
             if (fits) {
                 CHECK(st == UMI_OK);
                 if (st != UMI_OK) std::fprintf(stderr, "  plan: %s\n", umi_last_error());
+                // the replayed graph computed every curve of this batch
+                for (int64_t b = 0; b < n && st == UMI_OK; ++b)
+                    if (len[b] > 0) {
+                        CHECK(a.trend[off[b]] == 1.0f + (float)W[b]);
+                        CHECK(a.trend[off[b] + len[b] - 1] == 1.0f + (float)W[b]);
+                    }
             } else {
                 CHECK(st == UMI_ERR_INVALID_ARG);
             }
@@ -305,7 +351,7 @@ void check_noalloc()
         DevArrays a(std::max<int64_t>(total, 1));
         umi_launch lo = {uni(0, 3) == 0 ? UMI_MODE_PER_CURVE : UMI_MODE_PERSISTENT, 0, 0, 0,
                          nullptr, nullptr};
-        const long before = g_prepass;
+        const long before = g_prepass.load();
         const long mallocs = fake_hip::device_mallocs();
         const umi_status st = umi_detrend_batch_noalloc(a.flux, uni(0, 1) ? a.time : nullptr,
                                                         len.data(), n, W.data(), 2.0f, 5.0f, 5,
@@ -316,7 +362,7 @@ void check_noalloc()
     }
     std::vector<int64_t> big = {UMI_NOALLOC_MAX_SAMPLES, 1};
     std::vector<int32_t> w2 = {25, 25};
-    const long before = g_prepass;
+    const long before = g_prepass.load();
     CHECK(umi_detrend_batch_noalloc(reinterpret_cast<float*>(16), nullptr, big.data(), 2,
                                     w2.data(), 2.0f, 5.0f, 5, reinterpret_cast<float*>(16),
                                     nullptr, nullptr, nullptr) == UMI_ERR_UNSUPPORTED);
@@ -374,6 +420,151 @@ void check_copy_pool()
     for (auto& t : ts) t.join();
 }
 
+// The native serving loop: requests from three threads (empty ones, ones
+// larger than a step, one larger than the staging ring, gaps in time), all
+// completing with flux + W in their own output; invalid submissions refused;
+// a step whose estimate kernel fails reports its requests as failed and the
+// server goes on; shutdown finishes what was queued; nothing leaks.
+void check_server()
+{
+    struct Curve {
+        std::vector<float> flux, out;
+        std::vector<double> time;
+        int32_t W = 1;
+        bool with_time = true;
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        umi_server_config cfg{};
+        cfg.capacity = 400000;
+        cfg.max_step_samples = 50000;
+        cfg.staging_bytes = 3 << 20;  // 262,144 samples: the largest request does not fit
+        cfg.max_curves = 8;
+        cfg.max_W = 101;
+        cfg.max_inflight = pass == 0 ? 2 : 1;
+        cfg.copy_threads = 2;
+        umi_server* srv = nullptr;
+        CHECK(umi_server_create(&cfg, &srv) == UMI_OK);
+        if (!srv) return;
+        const int per_thread = std::max(8, g_rounds / 10), threads = 3;
+        std::vector<Curve> cv((size_t)(per_thread * threads));
+        std::mt19937_64 r0(77 + pass);
+        for (size_t i = 0; i < cv.size(); ++i) {
+            Curve& c = cv[i];
+            int64_t n = (int64_t)(r0() % 30000);
+            if (i % 17 == 5) n = 0;
+            if (i % 23 == 7) n = 60000 + (int64_t)(r0() % 40000);  // beyond one step
+            if (i == 11) n = 300000;                                // beyond the staging ring
+            c.flux.resize((size_t)n);
+            c.time.resize((size_t)n);
+            c.out.assign((size_t)n, -1.0f);
+            for (int64_t k = 0; k < n; ++k) {
+                c.flux[(size_t)k] = (float)(k % 1000) * 0.25f;
+                c.time[(size_t)k] = (double)k / 720.0 + (k > n / 2 ? 1.0 : 0.0);
+            }
+            c.W = (int32_t)(2 * (r0() % 51) + 1);
+            c.with_time = (i % 3) != 0;
+        }
+        // one W whose steps fail, in the second pass
+        const int32_t bad_W = pass == 1 ? 99 : 0;
+        if (bad_W) cv[4].W = cv[9].W = bad_W;
+        g_fail_W.store(bad_W);
+        auto submitter = [&](int t) {
+            for (int k = 0; k < per_thread; ++k) {
+                const size_t i = (size_t)(t * per_thread + k);
+                Curve& c = cv[i];
+                const umi_status st = umi_server_submit(
+                    srv, c.flux.data(), c.with_time ? c.time.data() : nullptr,
+                    (int64_t)c.flux.size(), c.W, 2.0f, 5.0f, (int32_t)(3 + (i % 2) * 2), -1.0,
+                    c.out.data(), (uint64_t)i);
+                CHECK(st == UMI_OK);
+            }
+        };
+        std::vector<std::thread> ts;
+        for (int t = 0; t < threads; ++t) ts.emplace_back(submitter, t);
+        // invalid submissions are refused and produce no completion
+        float dummy = 0.0f;
+        CHECK(umi_server_submit(srv, &dummy, nullptr, 1, 2, 2.0f, 5.0f, 5, -1.0, &dummy, 999999) ==
+              UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_submit(srv, &dummy, nullptr, 1, 103, 2.0f, 5.0f, 5, -1.0, &dummy,
+                                999999) == UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_submit(srv, &dummy, nullptr, 1, 5, INFINITY, 5.0f, 5, -1.0, &dummy,
+                                999999) == UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_submit(srv, &dummy, nullptr, 1, 5, 2.0f, 0.0f, 5, -1.0, &dummy, 999999) ==
+              UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_submit(srv, &dummy, nullptr, cfg.capacity + 1, 5, 2.0f, 5.0f, 5, -1.0,
+                                &dummy, 999999) == UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_submit(srv, nullptr, nullptr, 1, 5, 2.0f, 5.0f, 5, -1.0, &dummy, 999999) ==
+              UMI_ERR_INVALID_ARG);
+        for (auto& t : ts) t.join();
+        std::vector<int32_t> status(cv.size(), -1);
+        size_t got = 0;
+        std::vector<umi_server_completion> buf(16);
+        for (int spins = 0; got < cv.size() && spins < 20000; ++spins) {
+            int32_t k = 0;
+            CHECK(umi_server_poll(srv, buf.data(), (int32_t)buf.size(), 0.01, &k) == UMI_OK);
+            for (int32_t j = 0; j < k; ++j) {
+                const uint64_t tag = buf[(size_t)j].tag;
+                CHECK(tag < cv.size());
+                if (tag >= cv.size()) continue;
+                CHECK(status[tag] == -1);  // reported once
+                status[tag] = buf[(size_t)j].status;
+                CHECK(buf[(size_t)j].done >= buf[(size_t)j].launched &&
+                      buf[(size_t)j].launched >= buf[(size_t)j].admitted);
+                ++got;
+            }
+        }
+        CHECK(got == cv.size());
+        int64_t ok = 0, bad = 0;
+        for (size_t i = 0; i < cv.size(); ++i) {
+            const Curve& c = cv[i];
+            if (c.W == bad_W && !c.flux.empty()) {
+                CHECK(status[i] == UMI_ERR_DEVICE);
+                ++bad;
+                continue;
+            }
+            // a request that shared a step with a failing curve fails with it
+            if (bad_W != 0 && status[i] == UMI_ERR_DEVICE) {
+                ++bad;
+                continue;
+            }
+            CHECK(status[i] == UMI_OK);
+            bool same = true;
+            for (size_t k = 0; k < c.flux.size(); ++k)
+                same = same && c.out[k] == c.flux[k] + (float)c.W;
+            CHECK(same);
+            ++ok;
+        }
+        umi_server_stats st{};
+        CHECK(umi_server_stats_get(srv, &st) == UMI_OK);
+        CHECK(st.submitted == (int64_t)cv.size());
+        CHECK(st.completed + st.failed == (int64_t)cv.size());
+        CHECK(st.failed == bad && ok > 0 && (bad_W == 0 || bad >= 2));
+        CHECK(st.arena_used == 0 && st.arena_high_water <= cfg.capacity);
+        CHECK(st.steps > 0 && st.largest_step_samples >= 300000);
+        CHECK(st.staging_fallbacks >= 1);  // the request larger than the ring
+        CHECK(umi_server_reset_stats(srv) == UMI_OK);
+        // requests queued right before shutdown still complete
+        std::vector<float> f(1000, 2.0f), o(1000, 0.0f);
+        CHECK(umi_server_submit(srv, f.data(), nullptr, 1000, 7, 2.0f, 5.0f, 5, -1.0, o.data(),
+                                4242) == UMI_OK);
+        CHECK(umi_server_shutdown(srv) == UMI_OK);
+        int32_t k = 0;
+        CHECK(umi_server_poll(srv, buf.data(), (int32_t)buf.size(), 0.0, &k) == UMI_OK);
+        CHECK(k == 1 && buf[0].tag == 4242 && buf[0].status == UMI_OK);
+        CHECK(o[0] == 9.0f && o[999] == 9.0f);
+        CHECK(umi_server_submit(srv, f.data(), nullptr, 1000, 7, 2.0f, 5.0f, 5, -1.0, o.data(),
+                                1) == UMI_ERR_INVALID_ARG);
+        CHECK(umi_server_destroy(srv) == UMI_OK);
+        g_fail_W.store(0);
+    }
+    umi_server_config bad{};
+    umi_server* none = nullptr;
+    CHECK(umi_server_create(&bad, &none) == UMI_ERR_INVALID_ARG && none == nullptr);
+    bad.capacity = 1000;
+    bad.max_W = 4;
+    CHECK(umi_server_create(&bad, &none) == UMI_ERR_INVALID_ARG && none == nullptr);
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -387,17 +578,19 @@ int main(int argc, char** argv)
     check_noalloc();
     check_copy_kernel_lists();
     check_copy_pool();
+    check_server();
     umi_release();
     CHECK(fake_hip::live_device_blocks() == 0);
     CHECK(fake_hip::live_host_blocks() == 0);
     CHECK(fake_hip::live_events() == 0);
     CHECK(fake_hip::live_graphs() == 0);
+    CHECK(fake_hip::live_streams() == 0);
     CHECK(g_prepass > 0 && g_main > 0);
     if (g_failures) {
-        std::fprintf(stderr, "%d host checks failed\n", g_failures);
+        std::fprintf(stderr, "%d host checks failed\n", g_failures.load());
         return 1;
     }
-    std::printf("host checks ok (%ld pre-pass and %ld estimate launches checked)\n", g_prepass,
-                g_main);
+    std::printf("host checks ok (%ld pre-pass and %ld estimate launches checked)\n",
+                g_prepass.load(), g_main.load());
     return 0;
 }

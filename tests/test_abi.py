@@ -254,7 +254,9 @@ def test_serve_header_and_host_copy_many(lib):
     text = open(os.path.join(ROOT, "include", "umi_serve.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = sorted(set(re.findall(r"\b(umi_[a-z_]+)\s*\(", text)))
-    assert names == ["umi_copy_async", "umi_host_copy_many"]
+    assert names == ["umi_copy_async", "umi_host_copy_many", "umi_server_create",
+                     "umi_server_destroy", "umi_server_poll", "umi_server_reset_stats",
+                     "umi_server_shutdown", "umi_server_stats_get", "umi_server_submit"]
     for n in names:
         assert hasattr(lib.lib, n), n
     rng = np.random.default_rng(5)
@@ -313,6 +315,40 @@ def test_copy_async_rejects_bad_arguments(lib):
             lib.copy_async(args["dst"], args["src"], args["nbytes"], args["kind"], 0)
     f = lib.lib.umi_copy_async
     assert f(None, None, None, 1, 1, None) == 1 and f(None, None, None, -1, 1, None) == 1
+
+
+def test_server_validation_without_device(lib):
+    """The native server's entry points reject bad arguments before any
+    device call: config fields out of range, NULL handles and buffers."""
+    import ctypes
+    L = lib.lib
+
+    def cfg(**kw):
+        base = dict(capacity=1000, max_step_samples=0, staging_bytes=0, max_curves=0, max_W=0,
+                    max_inflight=0, copy_threads=0, device=0, reserved=0)
+        base.update(kw)
+        return lib.ServerConfig(**base)
+
+    for bad in [dict(capacity=0), dict(capacity=-5), dict(max_W=4), dict(max_W=2049),
+                dict(max_inflight=9), dict(copy_threads=65), dict(device=-1), dict(reserved=1),
+                dict(staging_bytes=1000), dict(max_curves=-1), dict(max_step_samples=-2)]:
+        h = ctypes.c_void_p(1234)
+        c = cfg(**bad)
+        assert L.umi_server_create(ctypes.byref(c), ctypes.byref(h)) == lib.UMI_ERR_INVALID_ARG, bad
+        assert h.value is None  # *out cleared
+    assert L.umi_server_create(None, None) == lib.UMI_ERR_INVALID_ARG
+    x = np.zeros(4, np.float32)
+    assert L.umi_server_submit(None, x.ctypes.data, None, 4, 5, 2.0, 5.0, 5, -1.0, x.ctypes.data,
+                               0) == lib.UMI_ERR_INVALID_ARG
+    n = ctypes.c_int32(7)
+    buf = (lib.ServerCompletion * 2)()
+    assert L.umi_server_poll(None, buf, 2, 0.0, ctypes.byref(n)) == lib.UMI_ERR_INVALID_ARG
+    st = lib.ServerStats()
+    assert L.umi_server_stats_get(None, ctypes.byref(st)) == lib.UMI_ERR_INVALID_ARG
+    assert L.umi_server_reset_stats(None) == lib.UMI_ERR_INVALID_ARG
+    assert L.umi_server_shutdown(None) == lib.UMI_ERR_INVALID_ARG
+    assert L.umi_server_destroy(None) == lib.UMI_OK
+    assert ctypes.sizeof(lib.ServerConfig) == 48 and ctypes.sizeof(lib.ServerCompletion) == 40
 
 
 def test_host_copy_many_with_many_small_copies(lib):

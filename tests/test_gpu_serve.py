@@ -27,9 +27,10 @@ def torch():
     return _t
 
 
-def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
+@pytest.mark.parametrize("scheduler", ["python", "native"])
+def test_serving_results_equal_alone_and_oracle(torch, oracle_lib, scheduler):
     import paper_2604_06602_amd as umi
-    from paper_2604_06602_amd.serve import GpuExecutor, Server
+    from paper_2604_06602_amd.serve import GpuExecutor, NativeServer, Server
 
     rng = np.random.default_rng(4)
     presets = [(2.0, 5.0), (3.0, 5.0), (1.0, 5.0), (10.0, 2.5)]
@@ -39,8 +40,13 @@ def test_serving_results_equal_alone_and_oracle(torch, oracle_lib):
         L = min(f.size, 30000)
         curves.append((f[:L], t[:L], W) + presets[i % 4])
     total = sum(cv[0].size for cv in curves)
-    ex = GpuExecutor(capacity=total // 2, max_curves=64, max_W=721)  # budget forces queueing
-    srv = Server(ex)
+    print("serving test: %s scheduler, %d curves" % (scheduler, len(curves)), flush=True)
+    if scheduler == "native":  # the library's own loop; small staging rings
+        srv = NativeServer(total // 2, max_curves=64, max_W=721, staging_bytes=16 << 20,
+                           max_step_samples=40000)
+    else:
+        ex = GpuExecutor(capacity=total // 2, max_curves=64, max_W=721)  # budget forces queueing
+        srv = Server(ex)
     futs = []
     for i, (f, t, W, a, c) in enumerate(curves):
         futs.append(srv.submit(f, t, W, alpha=a, c=c))
