@@ -295,6 +295,9 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-scheduler", choices=["native", "python"], default="native",
                     help="serving loop: the library's native scheduler, or the Python one")
+    ap.add_argument("--quantize", type=float, default=0.0, metavar="STEP",
+                    help="round the workload's flux to multiples of STEP (ties in every window; "
+                         "for timing the tie handling)")
     ap.add_argument("--no-serve-leg", action="store_true",
                     help="skip the short serving measurement of the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -335,6 +338,11 @@ def main(argv=None):
 
     log("generating workload %d" % args.workload)
     batch = synth.config_batch(args.workload)
+    if args.quantize > 0:
+        # heavy ties: every flux a multiple of the step (NaN stays NaN)
+        batch.flux[:] = (np.round(batch.flux.astype(np.float64) / args.quantize)
+                         * args.quantize).astype(np.float32)
+        log("flux quantised to multiples of %g" % args.quantize)
     alpha, c, iters = 2.0, 5.0, 5
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -456,14 +464,16 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl, "curves": int(batch.n_curves),
+        "config": {"workload": wl + ("_quantized_%g" % args.quantize if args.quantize > 0 else ""),
+                   "curves": int(batch.n_curves),
                    "samples": int(batch.n_samples),
                    "W": sorted(set(int(w) for w in batch.W)), "alpha": alpha, "c": c,
                    "iters": iters, "windows": windows, "mode": args.mode, "tuning": tuning,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "kernel": "umi_main_kernel",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": counted_traffic(args.workload),
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": counted_traffic(args.workload) if args.quantize == 0 else None,
                      "target_frac": TARGET_FRAC,
                      "target_met": achieved / PEAK_FP32_TFLOPS >= TARGET_FRAC,
                      "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",

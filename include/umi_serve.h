@@ -71,16 +71,17 @@ umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_
 /*
  * Native serving loop.  A server owns one device's resident arena (flux f32,
  * time f64 and trend f32 arrays of `capacity` samples), a replayable plan over
- * it, pinned staging rings, three streams (uploads, steps, downloads) and a
- * scheduler thread.  Requests -- one light curve each, with its own W, alpha
- * and c (Section 2; the Table 4 settings mix freely in one step) -- are
- * admitted first-in first-out while their samples fit the arena (each
- * admission group gets one contiguous range), staged into pinned memory and
- * uploaded by the copy kernel, and run as continuous-batching steps: every
- * uploaded group with the same iteration count joins the next step, up to
- * max_curves curves and max_step_samples samples, with up to max_inflight
- * steps on the device at once.  A finished step's trends are copied straight
- * into each request's `out` buffer and the request is reported complete.
+ * it, pinned staging rings, three streams (uploads, steps, downloads), a
+ * scheduler thread and a waiter thread.  Requests -- one light curve each,
+ * with its own W, alpha and c (Section 2; the Table 4 settings mix freely in
+ * one step) -- are admitted first-in first-out while their samples fit the
+ * arena (each admission group gets one contiguous range), staged into pinned
+ * memory and uploaded by the copy kernel, and run as continuous-batching
+ * steps: every uploaded group with the same iteration count joins the next
+ * step, up to max_curves curves and max_step_samples samples, with up to
+ * max_inflight steps on the device at once.  When a step's device work is
+ * done the waiter thread copies its trends straight into each request's
+ * `out` buffer and reports the requests complete.
  *
  * umi_server_submit queues a request and returns at once.  flux [n] float32,
  * time [n] float64 (or NULL: no gap breaks) and out [n] float32 are [host]
@@ -103,21 +104,24 @@ umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_
  * umi_server_shutdown finishes every queued request, stops the scheduler and
  * frees the device and pinned memory; completions stay available to
  * umi_server_poll.  umi_server_destroy shuts down (if not done yet) and frees
- * the server.  umi_server_stats fills *out with counters since creation or
+ * the server.  umi_server_stats_get fills *out with counters since creation or
  * the last umi_server_reset_stats.
  *
  * Errors of umi_server_create: a config field out of range gives
  * UMI_ERR_INVALID_ARG; device or pinned memory that cannot be allocated gives
  * UMI_ERR_NO_MEMORY; a runtime error UMI_ERR_DEVICE.  A failure inside the
- * scheduler thread fails every unresolved request with UMI_ERR_DEVICE and
- * stops it; later submits give UMI_ERR_INVALID_ARG.
+ * scheduler thread fails every request not yet launched with UMI_ERR_DEVICE
+ * (launched steps still complete) and stops it; later submits give
+ * UMI_ERR_INVALID_ARG.
  */
 typedef struct umi_server umi_server;
 
 typedef struct {
     int64_t capacity;         /* arena samples (> 0) */
-    int64_t max_step_samples; /* samples per step and admission group (0: 2^25); a
-                                 lone larger request runs as a step of its own */
+    int64_t max_step_samples; /* samples per step and admission group (0: 2^22); a
+                                 lone larger request runs as a step of its own;
+                                 it bounds how long a step's result copies take
+                                 when a backlog has built up */
     int64_t staging_bytes;    /* pinned upload ring (0: 4 GiB); the download ring
                                  is a third of it */
     int32_t max_curves;       /* curves per step (0: 4096) */
@@ -142,9 +146,10 @@ typedef struct {
     int64_t steps, step_curves, samples, largest_step_samples;
     int64_t arena_capacity, arena_used, arena_high_water;
     int64_t staging_fallbacks;  /* one-off pinned blocks for oversize groups */
-    double loop_s[4];           /* scheduler time: finish, admit, upload, launch */
-    double longest_iteration_s;
-    double longest_iteration_loop_s[4];
+    double loop_s[4];           /* seconds finishing steps (waiter thread), then
+                                   admitting, uploading, launching (scheduler) */
+    double longest_iteration_s; /* longest scheduler iteration */
+    double longest_iteration_loop_s[4];  /* its split as loop_s ([0] is 0) */
     double exec_s[4];           /* staging copy, upload enqueue, plan run, result copy */
 } umi_server_stats;
 

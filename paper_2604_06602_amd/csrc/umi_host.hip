@@ -591,6 +591,41 @@ int cu_count(int device)
 // of the library) and returns `s`.
 umi_status report_error(umi_status s, const std::string& msg) { return fail(s, msg); }
 
+umi_status host_copy_many(int which, void* const* dst, const void* const* src,
+                          const int64_t* bytes, int64_t n, int32_t threads);
+
+// The copy kernel over a list of copies whose both ends are device addresses
+// (pinned host memory at its device address): lists of at most kCopyMax
+// copies, each one launch.  Zero-byte copies are skipped.
+hipError_t enqueue_copy_list(uint8_t* const* dst, const uint8_t* const* src, const int64_t* bytes,
+                             int64_t n, hipStream_t stream)
+{
+    CopyBatch cb;
+    std::memset(&cb, 0, sizeof cb);
+    int64_t pieces = 0;
+    for (int64_t i = 0; i <= n; ++i) {
+        const bool full = cb.n == kCopyMax ||
+                          (i < n && pieces + (bytes[i] + kCopyPieceBytes - 1) / kCopyPieceBytes >
+                                        (int64_t)INT32_MAX);
+        if ((i == n || full) && cb.n > 0) {
+            cb.first[cb.n] = (int32_t)pieces;
+            const hipError_t e = launch_copy(cb, stream);
+            if (e != hipSuccess) return e;
+            std::memset(&cb, 0, sizeof cb);
+            pieces = 0;
+        }
+        if (i == n) break;
+        if (bytes[i] == 0) continue;
+        cb.first[cb.n] = (int32_t)pieces;
+        cb.src[cb.n] = src[i];
+        cb.dst[cb.n] = dst[i];
+        cb.bytes[cb.n] = bytes[i];
+        pieces += (bytes[i] + kCopyPieceBytes - 1) / kCopyPieceBytes;
+        ++cb.n;
+    }
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------------------
 // direct calls: curves at explicit offsets
 
@@ -745,10 +780,13 @@ class CopyPool {
     size_t workers_ = 0;
 };
 
-CopyPool& copy_pool()
+// Pool 0 serves umi_host_copy_many; pool 1 the serving loop's result copies,
+// which run on another thread than its staging copies and must not wait for
+// them.
+CopyPool& copy_pool(int which = 0)
 {
-    static CopyPool* pool = new CopyPool();  // intentionally never freed
-    return *pool;
+    static CopyPool* pools[2] = {new CopyPool(), new CopyPool()};  // intentionally never freed
+    return *pools[which & 1];
 }
 
 }  // namespace
@@ -1302,31 +1340,42 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.7.0"; }
+const char* umi_version(void) { return "umi-mi355x 0.8.0"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 
 umi_status umi_host_copy_many(void* const* dst, const void* const* src, const int64_t* bytes,
                               int64_t n, int32_t threads)
 {
-    if (n < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: n < 0");
+    return umi::host_copy_many(0, dst, src, bytes, n, threads);
+}
+
+}  // extern "C"
+
+namespace umi {
+
+// umi_host_copy_many on copy pool `which` (0 or 1).
+umi_status host_copy_many(int which, void* const* dst, const void* const* src,
+                          const int64_t* bytes, int64_t n, int32_t threads)
+{
+    if (n < 0) return fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: n < 0");
     if (threads < 1 || threads > UMI_HOST_COPY_MAX_THREADS)
-        return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: threads out of range");
+        return fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: threads out of range");
     if (n == 0) return UMI_OK;
     if (!dst || !src || !bytes)
-        return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL array");
-    umi::CopyJob job;
+        return fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL array");
+    CopyJob job;
     job.dst = dst;
     job.src = src;
     job.bytes = bytes;
     job.first.resize(size_t(n) + 1);
     int64_t pieces = 0;
     for (int64_t i = 0; i < n; ++i) {
-        if (bytes[i] < 0) return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: bytes < 0");
+        if (bytes[i] < 0) return fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: bytes < 0");
         if (bytes[i] > 0 && (!dst[i] || !src[i]))
-            return umi::fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL pointer");
+            return fail(UMI_ERR_INVALID_ARG, "umi_host_copy_many: NULL pointer");
         job.first[size_t(i)] = pieces;
-        pieces += (bytes[i] + umi::kCopyPiece - 1) / umi::kCopyPiece;
+        pieces += (bytes[i] + kCopyPiece - 1) / kCopyPiece;
     }
     job.first[size_t(n)] = pieces;
     if (pieces == 0) return UMI_OK;
@@ -1335,9 +1384,13 @@ umi_status umi_host_copy_many(void* const* dst, const void* const* src, const in
         job.work();
         return UMI_OK;
     }
-    umi::copy_pool().run(job, int(useful));
+    copy_pool(which).run(job, int(useful));
     return UMI_OK;
 }
+
+}  // namespace umi
+
+extern "C" {
 
 umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_t* bytes,
                           int64_t n, int32_t kind, void* stream)
@@ -1376,30 +1429,16 @@ umi_status umi_copy_async(void* const* dst, const void* const* src, const int64_
                                       (q - static_cast<char*>(a.hostPointer));
             }
         }
-        // lists of at most kCopyMax copies, each as one launch of the copy kernel
-        umi::CopyBatch cb;
-        std::memset(&cb, 0, sizeof cb);
-        int64_t pieces = 0;
-        for (int64_t i = 0; i <= n; ++i) {
-            const bool full = cb.n == umi::kCopyMax ||
-                              (i < n && pieces + (bytes[i] + umi::kCopyPieceBytes - 1) /
-                                                     umi::kCopyPieceBytes > (int64_t)INT32_MAX);
-            if ((i == n || full) && cb.n > 0) {
-                cb.first[cb.n] = (int32_t)pieces;
-                const hipError_t e = umi::launch_copy(cb, static_cast<hipStream_t>(stream));
-                if (e != hipSuccess) return umi::fail_hip(e, "umi_copy_async: copy kernel");
-                std::memset(&cb, 0, sizeof cb);
-                pieces = 0;
-            }
-            if (i == n) break;
-            if (bytes[i] == 0) continue;
-            cb.first[cb.n] = (int32_t)pieces;
-            cb.src[cb.n] = static_cast<const uint8_t*>(kind == UMI_COPY_H2D ? hdev[(size_t)i] : src[i]);
-            cb.dst[cb.n] = static_cast<uint8_t*>(kind == UMI_COPY_D2H ? hdev[(size_t)i] : dst[i]);
-            cb.bytes[cb.n] = bytes[i];
-            pieces += (bytes[i] + umi::kCopyPieceBytes - 1) / umi::kCopyPieceBytes;
-            ++cb.n;
+        // both ends at device addresses, then lists of the copy kernel
+        std::vector<uint8_t*> d((size_t)n);
+        std::vector<const uint8_t*> sr((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            sr[(size_t)i] = static_cast<const uint8_t*>(kind == UMI_COPY_H2D ? hdev[(size_t)i] : src[i]);
+            d[(size_t)i] = static_cast<uint8_t*>(kind == UMI_COPY_D2H ? hdev[(size_t)i] : dst[i]);
         }
+        const hipError_t e = umi::enqueue_copy_list(d.data(), sr.data(), bytes, n,
+                                                    static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return umi::fail_hip(e, "umi_copy_async: copy kernel");
         return UMI_OK;
     }
     const hipMemcpyKind k = kind == UMI_COPY_H2D ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;

@@ -1556,20 +1556,44 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         for (int i = nv + tid; i < npad; i += kMainThreads) sm.sortbuf[i] = ~0ull;
         __syncthreads();
 
-        // --- bitonic sort of sortbuf[0, npad) ascending ---
-        for (int kk = 2; kk <= npad; kk <<= 1) {
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                for (int cix = tid; cix < (npad >> 1); cix += kMainThreads) {
-                    const int i = 2 * cix - (cix & (jj - 1));
-                    const int l = i + jj;
-                    const uint64_t a = sm.sortbuf[i], b = sm.sortbuf[l];
-                    const bool asc = (i & kk) == 0;
-                    if ((a > b) == asc) {
-                        sm.sortbuf[i] = b;
-                        sm.sortbuf[l] = a;
-                    }
+        if ((kFeat & kFeatSplit) && npad <= kMainThreads) {
+            // --- a small tile: every element counts the elements below it ---
+            // The (key, index) pairs are distinct, so the counts are the
+            // ranks the sorting network would give, without a barrier per
+            // network stage; padding [nv, npad) already holds ~0.
+            uint64_t mine = 0;
+            uint32_t rank = 0;
+            if (tid < nv) {
+                mine = sm.sortbuf[tid];
+                // eight loads ahead of their compares; the padding up to the
+                // next multiple of eight (within npad) holds ~0 and counts 0
+                for (int j0 = 0; j0 < nv; j0 += 8) {
+                    uint64_t v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = sm.sortbuf[j0 + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) rank += v[u] < mine ? 1u : 0u;
                 }
-                __syncthreads();
+            }
+            __syncthreads();
+            if (tid < nv) sm.sortbuf[rank] = mine;
+            __syncthreads();
+        } else {
+            // --- bitonic sort of sortbuf[0, npad) ascending ---
+            for (int kk = 2; kk <= npad; kk <<= 1) {
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int cix = tid; cix < (npad >> 1); cix += kMainThreads) {
+                        const int i = 2 * cix - (cix & (jj - 1));
+                        const int l = i + jj;
+                        const uint64_t a = sm.sortbuf[i], b = sm.sortbuf[l];
+                        const bool asc = (i & kk) == 0;
+                        if ((a > b) == asc) {
+                            sm.sortbuf[i] = b;
+                            sm.sortbuf[l] = a;
+                        }
+                    }
+                    __syncthreads();
+                }
             }
         }
 

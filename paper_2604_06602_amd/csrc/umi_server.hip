@@ -4,13 +4,15 @@
 // through a replayable plan.
 //
 // Threads.  Callers submit and poll from any thread.  One scheduler thread
-// owns the arena, the staging rings, the groups and the steps: it admits
-// waiting requests, stages and uploads them, launches steps and finishes
-// completed ones.  One waiter thread blocks on the oldest in-flight step's
-// completion event and wakes the scheduler, so completions are noticed at
-// once without the scheduler polling.  `mu_` guards the waiting queue, the
-// shutdown flag and the statistics; `cmu_` the completion queue; `wmu_` the
-// waiter's queue.
+// admits waiting requests, stages and uploads them and launches steps; one
+// waiter thread blocks on each in-flight step's completion event in launch
+// order, then finishes the step (copies every result into its request's
+// output, releases the step's memory, reports the completions) and wakes the
+// scheduler, so result copies never hold up admission and launches.  `mu`
+// guards the waiting queue, the shutdown flags and the statistics; `rmu` the
+// arena, the staging rings, the event pool, upload bookkeeping and the
+// in-flight count (taken after `mu` where both are held); `cmu` the
+// completion queue; `wmu` the waiter's queue.
 //
 // Device work per step, on three streams: uploads (the copy kernel reads the
 // pinned staging ring), the step itself (the plan's graph on the compute
@@ -38,11 +40,16 @@
 #include <vector>
 
 #include "umi.h"
+#include "umi_internal.h"
 #include "umi_serve.h"
 
 namespace umi {
 
 umi_status report_error(umi_status s, const std::string& msg);
+hipError_t enqueue_copy_list(uint8_t* const* dst, const uint8_t* const* src, const int64_t* bytes,
+                             int64_t n, hipStream_t stream);
+umi_status host_copy_many(int which, void* const* dst, const void* const* src,
+                          const int64_t* bytes, int64_t n, int32_t threads);
 
 namespace srv {
 
@@ -117,6 +124,7 @@ class Ring {
   public:
     static constexpr int64_t kAlign = 256;
     uint8_t* base = nullptr;
+    uint8_t* dev = nullptr;  // base's device address
     int64_t size = 0;
 
     // a block of at least n bytes as (id, offset); false when it does not fit now
@@ -188,6 +196,7 @@ struct Upload {
     bool in_ring = false;
     uint64_t ring_id = 0;
     uint8_t* oneoff = nullptr;
+    uint8_t* oneoff_dev = nullptr;
     bool staging_freed = false;
     int groups_left = 0;  // groups not yet finished
 };
@@ -209,7 +218,6 @@ struct Step {
     std::vector<int64_t> out_pos;  // byte offset of each group's trend in the block
     int64_t samples = 0, curves = 0;
     double launched = 0.0;
-    std::atomic<bool> ready{false};
 };
 
 }  // namespace srv
@@ -228,9 +236,12 @@ struct umi_server {
     float* trend = nullptr;
     umi_plan* plan = nullptr;
     hipStream_t up_stream = nullptr, compute = nullptr, down_stream = nullptr;
+    // guarded by rmu
+    std::mutex rmu;
     umi::srv::Ring ring_in, ring_out;
     umi::srv::Arena arena{0};
-    std::vector<hipEvent_t> event_pool;  // scheduler thread only
+    std::vector<hipEvent_t> event_pool;
+    int inflight = 0;  // launched steps not yet finished
 
     // guarded by mu
     std::mutex mu;
@@ -254,7 +265,6 @@ struct umi_server {
     // scheduler-owned state
     std::deque<Group*> to_upload;  // admitted, not uploaded
     std::deque<Group*> uploaded;   // uploaded, not launched
-    std::deque<Step*> inflight;    // launched, oldest first
 
     std::thread scheduler, waiter;
     bool shut = false;
@@ -281,6 +291,7 @@ struct umi_server {
         ccv.notify_all();
     }
 
+    // The helpers below are called with rmu held.
     hipEvent_t take_event()
     {
         if (!event_pool.empty()) {
@@ -327,6 +338,7 @@ struct umi_server {
     {
         bool any = false;
         Group* g = nullptr;
+        std::lock_guard<std::mutex> rk(rmu);
         while (!waiting.empty()) {
             Req& r = waiting.front();
             const int64_t off = arena.alloc(r.n);
@@ -373,17 +385,18 @@ struct umi_server {
         Upload* u = new Upload();
         int64_t off = 0;
         uint8_t* base = nullptr;
-        if (gs.size() > 1 && !ring_in.alloc(bytes, &u->ring_id, &off)) {
-            // not all of them fit now: the first alone
-            gs.resize(1);
-            bytes = (12 * gs[0]->size + align - 1) / align * align;
-        } else if (gs.size() > 1) {
-            u->in_ring = true;
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            if (gs.size() > 1 && !ring_in.alloc(bytes, &u->ring_id, &off)) {
+                // not all of them fit now: the first alone
+                gs.resize(1);
+                bytes = (12 * gs[0]->size + align - 1) / align * align;
+            } else if (gs.size() > 1) {
+                u->in_ring = true;
+            }
+            if (!u->in_ring && ring_in.alloc(bytes, &u->ring_id, &off)) u->in_ring = true;
         }
         if (u->in_ring) {
-            base = ring_in.base + off;
-        } else if (ring_in.alloc(bytes, &u->ring_id, &off)) {
-            u->in_ring = true;
             base = ring_in.base + off;
         } else if (bytes > ring_in.size) {
             // larger than the whole ring (a lone oversize request): a one-off block
@@ -394,6 +407,12 @@ struct umi_server {
             }
             u->oneoff = static_cast<uint8_t*>(p);
             base = u->oneoff;
+            if (hipHostGetDevicePointer(reinterpret_cast<void**>(&u->oneoff_dev), p, 0) !=
+                hipSuccess) {
+                (void)hipHostFree(p);
+                delete u;
+                throw std::runtime_error("pinned staging has no device address");
+            }
             std::lock_guard<std::mutex> lk(mu);
             ++st.staging_fallbacks;
         } else {
@@ -404,12 +423,15 @@ struct umi_server {
         std::vector<void*> dst;
         std::vector<const void*> src;
         std::vector<int64_t> nb;
-        std::vector<void*> hd;
-        std::vector<const void*> hs;
+        std::vector<uint8_t*> hd;
+        std::vector<const uint8_t*> hs;
         std::vector<int64_t> hn;
+        // the copy kernel reads the block at its device address
+        uint8_t* const dbase = u->in_ring ? ring_in.dev + off : u->oneoff_dev;
         int64_t gbase = 0;
         for (Group* g : gs) {
             uint8_t* b = base + gbase;
+            const uint8_t* db = dbase + gbase;
             int64_t pos = 0;
             for (const Req& r : g->reqs) {
                 if (r.time) {
@@ -424,26 +446,31 @@ struct umi_server {
                 nb.push_back(4 * r.n);
                 pos += r.n;
             }
-            hd.push_back(time + g->offset);
-            hs.push_back(b);
+            hd.push_back(reinterpret_cast<uint8_t*>(time + g->offset));
+            hs.push_back(db);
             hn.push_back(8 * g->size);
-            hd.push_back(flux + g->offset);
-            hs.push_back(b + 8 * g->size);
+            hd.push_back(reinterpret_cast<uint8_t*>(flux + g->offset));
+            hs.push_back(db + 8 * g->size);
             hn.push_back(4 * g->size);
             gbase += (12 * g->size + align - 1) / align * align;
         }
         if (umi_host_copy_many(dst.data(), src.data(), nb.data(), (int64_t)dst.size(),
                                cfg.copy_threads) != UMI_OK) {
+            std::lock_guard<std::mutex> rk(rmu);
             free_staging(u);
             delete u;
             throw std::runtime_error("staging copy failed");
         }
         const double t1 = umi::srv::now_s();
-        u->ev = take_event();
-        if (umi_copy_async(hd.data(), hs.data(), hn.data(), (int64_t)hd.size(),
-                           UMI_COPY_H2D | UMI_COPY_KERNEL, up_stream) != UMI_OK ||
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            u->ev = take_event();
+        }
+        if (umi::enqueue_copy_list(hd.data(), hs.data(), hn.data(), (int64_t)hd.size(),
+                                   up_stream) != hipSuccess ||
             hipEventRecord(u->ev, up_stream) != hipSuccess) {
             (void)hipStreamSynchronize(up_stream);
+            std::lock_guard<std::mutex> rk(rmu);
             put_event(u->ev);
             free_staging(u);
             delete u;
@@ -492,20 +519,25 @@ struct umi_server {
         (void)hipStreamSynchronize(down_stream);
         const double now = umi::srv::now_s();
         std::vector<umi_server_completion> cs;
-        for (Group* g : s->groups) {
-            for (const Req& r : g->reqs) cs.push_back(completion(r, status, now));
-            arena.release(g->offset, g->size);
-            group_done(g);
-            delete g;
+        int64_t used;
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            for (Group* g : s->groups) {
+                for (const Req& r : g->reqs) cs.push_back(completion(r, status, now));
+                arena.release(g->offset, g->size);
+                group_done(g);
+                delete g;
+            }
+            if (s->out_in_ring) ring_out.release(s->out_id);
+            if (s->out_oneoff) (void)hipHostFree(s->out_oneoff);
+            put_event(s->computed);
+            put_event(s->done);
+            used = arena.used();
         }
         publish(cs);
-        if (s->out_in_ring) ring_out.release(s->out_id);
-        if (s->out_oneoff) (void)hipHostFree(s->out_oneoff);
-        put_event(s->computed);
-        put_event(s->done);
         std::lock_guard<std::mutex> lk(mu);
         st.failed += s->curves;
-        st.arena_used = arena.used();
+        st.arena_used = used;
         delete s;
     }
 
@@ -549,9 +581,14 @@ struct umi_server {
         // the result block, and the download of every group's trend into it
         const int64_t bytes = 4 * s->samples;
         int64_t off = 0;
-        if (ring_out.alloc(bytes, &s->out_id, &off)) {
-            s->out_in_ring = true;
+        uint8_t* out_dev = nullptr;  // the result block's device address
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            s->out_in_ring = ring_out.alloc(bytes, &s->out_id, &off);
+        }
+        if (s->out_in_ring) {
             s->out_base = ring_out.base + off;
+            out_dev = ring_out.dev + off;
         } else {
             void* p = nullptr;  // larger than the free ring: a one-off block
             if (hipHostMalloc(&p, (size_t)std::max<int64_t>(bytes, 1), hipHostMallocDefault) !=
@@ -561,21 +598,26 @@ struct umi_server {
             }
             s->out_oneoff = static_cast<uint8_t*>(p);
             s->out_base = s->out_oneoff;
+            if (hipHostGetDevicePointer(reinterpret_cast<void**>(&out_dev), p, 0) != hipSuccess) {
+                fail_step(s, UMI_ERR_DEVICE);
+                return;
+            }
             std::lock_guard<std::mutex> lk(mu);
             ++st.staging_fallbacks;
         }
-        std::vector<void*> d;
-        std::vector<const void*> src;
+        std::vector<uint8_t*> d;
+        std::vector<const uint8_t*> src;
         std::vector<int64_t> nb;
         int64_t pos = 0;
         for (Group* g : s->groups) {
             s->out_pos.push_back(pos);
-            d.push_back(s->out_base + pos);
-            src.push_back(trend + g->offset);
+            d.push_back(out_dev + pos);
+            src.push_back(reinterpret_cast<const uint8_t*>(trend + g->offset));
             nb.push_back(4 * g->size);
             pos += 4 * g->size;
         }
         try {
+            std::lock_guard<std::mutex> rk(rmu);
             s->computed = take_event();
             s->done = take_event();
         } catch (...) {
@@ -584,27 +626,42 @@ struct umi_server {
         }
         if (hipEventRecord(s->computed, compute) != hipSuccess ||
             hipStreamWaitEvent(down_stream, s->computed, 0) != hipSuccess ||
-            umi_copy_async(d.data(), src.data(), nb.data(), (int64_t)d.size(),
-                           UMI_COPY_D2H | UMI_COPY_KERNEL, down_stream) != UMI_OK ||
+            umi::enqueue_copy_list(d.data(), src.data(), nb.data(), (int64_t)d.size(),
+                                   down_stream) != hipSuccess ||
             hipEventRecord(s->done, down_stream) != hipSuccess) {
             fail_step(s, UMI_ERR_DEVICE);
             return;
         }
         *t_plan += umi::srv::now_s() - t0;
-        inflight.push_back(s);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            st.steps += 1;
+            st.step_curves += s->curves;
+            st.largest_step_samples = std::max(st.largest_step_samples, s->samples);
+        }
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            ++inflight;
+        }
         {
             std::lock_guard<std::mutex> lk(wmu);
-            wait_q.push_back(s);
+            wait_q.push_back(s);  // the waiter owns the step from here on
         }
         wcv.notify_one();
-        std::lock_guard<std::mutex> lk(mu);
-        st.steps += 1;
-        st.step_curves += s->curves;
-        st.largest_step_samples = std::max(st.largest_step_samples, s->samples);
     }
 
-    // -- completion ---------------------------------------------------------
-    void finish(Step* s, double* t_res)
+    int inflight_count()
+    {
+        std::lock_guard<std::mutex> rk(rmu);
+        return inflight;
+    }
+
+    // -- completion (waiter thread) -------------------------------------------
+    // The step's device work is done: copy every result into its request's
+    // output (on a copy pool of its own, so these copies never wait for the
+    // scheduler's staging copies), release the step's memory, report its
+    // completions.
+    void finish(Step* s)
     {
         const double t0 = umi::srv::now_s();
         std::vector<void*> d;
@@ -620,43 +677,55 @@ struct umi_server {
                 pos += r.n;
             }
         }
-        const umi_status cs = umi_host_copy_many(d.data(), src.data(), nb.data(),
-                                                 (int64_t)d.size(), cfg.copy_threads);
+        const umi_status cs = umi::host_copy_many(1, d.data(), src.data(), nb.data(),
+                                                  (int64_t)d.size(), cfg.copy_threads);
         const double now = umi::srv::now_s();
-        int64_t samples = 0;
+        int64_t samples = 0, used;
         std::vector<umi_server_completion> done;
         done.reserve((size_t)s->curves);
-        for (Group* g : s->groups) {
-            for (const Req& r : g->reqs) {
-                done.push_back(completion(r, cs, now));
-                samples += r.n;
+        {
+            std::lock_guard<std::mutex> rk(rmu);
+            for (Group* g : s->groups) {
+                for (const Req& r : g->reqs) {
+                    done.push_back(completion(r, cs, now));
+                    samples += r.n;
+                }
+                arena.release(g->offset, g->size);
+                group_done(g);
+                delete g;
             }
-            arena.release(g->offset, g->size);
-            group_done(g);
-            delete g;
+            if (s->out_in_ring) ring_out.release(s->out_id);
+            if (s->out_oneoff) (void)hipHostFree(s->out_oneoff);
+            put_event(s->computed);
+            put_event(s->done);
+            --inflight;
+            used = arena.used();
         }
         publish(done);
-        if (s->out_in_ring) ring_out.release(s->out_id);
-        if (s->out_oneoff) (void)hipHostFree(s->out_oneoff);
-        put_event(s->computed);
-        put_event(s->done);
-        *t_res += umi::srv::now_s() - t0;
-        std::lock_guard<std::mutex> lk(mu);
-        if (cs == UMI_OK) {
-            st.completed += s->curves;
-            st.samples += samples;
-        } else {
-            st.failed += s->curves;
+        const double t1 = umi::srv::now_s();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (cs == UMI_OK) {
+                st.completed += s->curves;
+                st.samples += samples;
+            } else {
+                st.failed += s->curves;
+            }
+            st.arena_used = used;
+            st.exec_s[3] += t1 - t0;
+            st.loop_s[0] += t1 - t0;
+            ++wake;
         }
-        st.arena_used = arena.used();
+        cv.notify_all();
         delete s;
     }
 
-    // Everything not yet resolved fails with `status` (called on a scheduler
-    // error, after which the scheduler stops).
+    // Everything waiting, admitted or uploaded and not yet launched fails
+    // with `status` (called on a scheduler error, after which the scheduler
+    // stops); launched steps are finished by the waiter as usual.
     void fail_all(umi_status status)
     {
-        for (hipStream_t q : {up_stream, compute, down_stream}) (void)hipStreamSynchronize(q);
+        (void)hipStreamSynchronize(up_stream);
         const double now = umi::srv::now_s();
         std::deque<Req> w;
         {
@@ -667,36 +736,26 @@ struct umi_server {
         }
         std::vector<umi_server_completion> cs;
         for (const Req& r : w) cs.push_back(completion(r, status, now));
+        int64_t n = 0, used;
         {
-            // the waiter touches no step that has left its queue
-            std::lock_guard<std::mutex> lk(wmu);
-            wait_q.clear();
+            std::lock_guard<std::mutex> rk(rmu);
+            auto drop = [&](Group* g) {
+                for (const Req& r : g->reqs) cs.push_back(completion(r, status, now));
+                n += (int64_t)g->reqs.size();
+                arena.release(g->offset, g->size);
+                group_done(g);
+                delete g;
+            };
+            for (Group* g : to_upload) drop(g);
+            for (Group* g : uploaded) drop(g);
+            used = arena.used();
         }
-        int64_t n = 0;
-        auto drop = [&](Group* g) {
-            for (const Req& r : g->reqs) cs.push_back(completion(r, status, now));
-            n += (int64_t)g->reqs.size();
-            arena.release(g->offset, g->size);
-            group_done(g);
-            delete g;
-        };
-        for (Group* g : to_upload) drop(g);
-        for (Group* g : uploaded) drop(g);
         to_upload.clear();
         uploaded.clear();
-        for (Step* s : inflight) {
-            for (Group* g : s->groups) drop(g);
-            if (s->out_in_ring) ring_out.release(s->out_id);
-            if (s->out_oneoff) (void)hipHostFree(s->out_oneoff);
-            put_event(s->computed);
-            put_event(s->done);
-            delete s;
-        }
-        inflight.clear();
         publish(cs);
         std::lock_guard<std::mutex> lk(mu);
         st.failed += n;
-        st.arena_used = arena.used();
+        st.arena_used = used;
     }
 
     // -- threads ------------------------------------------------------------
@@ -705,27 +764,15 @@ struct umi_server {
         (void)hipSetDevice(device);
         for (;;) {
             Step* s = nullptr;
-            hipEvent_t ev = nullptr;
             {
                 std::unique_lock<std::mutex> lk(wmu);
                 wcv.wait(lk, [&] { return waiter_stop || !wait_q.empty(); });
                 if (wait_q.empty()) return;  // stopping, nothing left
                 s = wait_q.front();
-                ev = s->done;  // pooled events outlive this thread
-            }
-            (void)hipEventSynchronize(ev);
-            {
-                // the step is only touched while it is still queued here
-                std::lock_guard<std::mutex> lk(wmu);
-                if (wait_q.empty() || wait_q.front() != s) continue;
                 wait_q.pop_front();
-                s->ready.store(true);
             }
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                ++wake;
-            }
-            cv.notify_all();
+            (void)hipEventSynchronize(s->done);
+            finish(s);
         }
     }
 
@@ -735,17 +782,9 @@ struct umi_server {
         using umi::srv::now_s;
         try {
             for (;;) {
-                const double t0 = now_s();
-                double tc = 0.0, te = 0.0, tp = 0.0, tr = 0.0;
-                bool progress = false;
-                // completions first: they free memory for admissions
-                while (!inflight.empty() && inflight.front()->ready.load()) {
-                    Step* s = inflight.front();
-                    inflight.pop_front();
-                    finish(s, &tr);
-                    progress = true;
-                }
                 const double t1 = now_s();
+                double tc = 0.0, te = 0.0, tp = 0.0;
+                bool progress = false;
                 uint64_t seen;
                 bool stop = false;
                 {
@@ -757,30 +796,29 @@ struct umi_server {
                 const double t2 = now_s();
                 while (upload(&tc, &te)) progress = true;
                 const double t3 = now_s();
-                while (!uploaded.empty() && (int)inflight.size() < cfg.max_inflight) {
+                while (!uploaded.empty() && inflight_count() < cfg.max_inflight) {
                     launch(next_step(), &tp);
                     progress = true;
                 }
                 const double t4 = now_s();
                 {
                     std::lock_guard<std::mutex> lk(mu);
-                    st.loop_s[0] += t1 - t0;
                     st.loop_s[1] += t2 - t1;
                     st.loop_s[2] += t3 - t2;
                     st.loop_s[3] += t4 - t3;
                     st.exec_s[0] += tc;
                     st.exec_s[1] += te;
                     st.exec_s[2] += tp;
-                    st.exec_s[3] += tr;
-                    if (t4 - t0 > st.longest_iteration_s) {
-                        st.longest_iteration_s = t4 - t0;
-                        st.longest_iteration_loop_s[0] = t1 - t0;
+                    if (t4 - t1 > st.longest_iteration_s) {
+                        st.longest_iteration_s = t4 - t1;
+                        st.longest_iteration_loop_s[0] = 0.0;
                         st.longest_iteration_loop_s[1] = t2 - t1;
                         st.longest_iteration_loop_s[2] = t3 - t2;
                         st.longest_iteration_loop_s[3] = t4 - t3;
                     }
                 }
-                const bool idle = inflight.empty() && uploaded.empty() && to_upload.empty();
+                const bool idle =
+                    uploaded.empty() && to_upload.empty() && inflight_count() == 0;
                 if (stop && idle) break;
                 if (progress) continue;
                 std::unique_lock<std::mutex> lk(mu);
@@ -854,7 +892,7 @@ umi_status umi_server_create(const umi_server_config* config, umi_server** out)
     *out = nullptr;
     if (!config) return report_error(UMI_ERR_INVALID_ARG, "umi_server_create: config is NULL");
     umi_server_config c = *config;
-    if (c.max_step_samples == 0) c.max_step_samples = int64_t(1) << 25;
+    if (c.max_step_samples == 0) c.max_step_samples = int64_t(1) << 22;
     if (c.staging_bytes == 0) c.staging_bytes = int64_t(4) << 30;
     if (c.max_curves == 0) c.max_curves = 4096;
     if (c.max_W == 0) c.max_W = 721;
@@ -903,11 +941,18 @@ umi_status umi_server_create(const umi_server_config* config, umi_server** out)
         } else {
             s->ring_in.base = static_cast<uint8_t*>(p);
             s->ring_in.size = c.staging_bytes;
-            if ((e = hipHostMalloc(&p, (size_t)out_bytes, hipHostMallocDefault)) != hipSuccess) {
+            if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->ring_in.dev), p, 0)) !=
+                hipSuccess) {
+                hip_fail(e, "pinned staging device address");
+            } else if ((e = hipHostMalloc(&p, (size_t)out_bytes, hipHostMallocDefault)) !=
+                       hipSuccess) {
                 hip_fail(e, "pinned results");
             } else {
                 s->ring_out.base = static_cast<uint8_t*>(p);
                 s->ring_out.size = out_bytes;
+                if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->ring_out.dev), p,
+                                                 0)) != hipSuccess)
+                    hip_fail(e, "pinned results device address");
             }
         }
     }

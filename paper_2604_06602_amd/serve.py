@@ -815,7 +815,9 @@ class NativeServer:
     each, with the plan workspace).  Times are Python's perf_counter clock,
     which is the clock the library stamps completions with (CLOCK_MONOTONIC)."""
 
-    MAX_STEP_SAMPLES = Server.MAX_STEP_SAMPLES
+    # smaller than the Python loop's: after a hiccup the backlog then runs in
+    # steps whose result copies stay short
+    MAX_STEP_SAMPLES = 1 << 22
 
     def __init__(self, capacity: int, max_curves: int = 4096, max_W: int = 721, device: int = 0,
                  max_step_samples: int | None = None, max_inflight: int = 2,
