@@ -31,6 +31,7 @@ with ``FakeExecutor``.
 """
 from __future__ import annotations
 
+import atexit
 import itertools
 import threading
 import time as _time
@@ -845,6 +846,9 @@ class NativeServer:
         self._poller = threading.Thread(target=self._poll_loop, name="umi-serve-native",
                                         daemon=True)
         self._poller.start()
+        # a server left open is shut down before the interpreter exits, so the
+        # library's threads never outlive the process's teardown
+        atexit.register(self.close)
 
     def submit(self, flux, time=None, W: int = 361, alpha: float = 2.0, c: float = 5.0,
                iters: int = 5, arrival: float | None = None) -> Future:
@@ -939,6 +943,7 @@ class NativeServer:
             if self._closed:
                 return
             self._closed = True
+        atexit.unregister(self.close)
         self._lib.lib.umi_server_shutdown(self._h)
         self._stop = True
         self._poller.join(timeout)

@@ -128,3 +128,67 @@ def test_executor_device_memory_stays_within_its_budget(torch):
     del ex
     assert used <= budget + 3 * (2 << 20) + (1 << 20), (used, budget)
     assert used >= capacity * (BYTES_PER_SAMPLE - 1)  # the estimate is not loose either
+
+
+def test_native_server_steps_iterations_and_memory(torch, oracle_lib):
+    """The native scheduler: requests larger than a step (each a step of its
+    own), two iteration counts (never mixed in a step), curves without times
+    (no gap breaks), empty requests and an arena smaller than the whole load
+    (admission waits for memory); every result equals the curve run alone
+    through the C ABI with its settings (trend tolerance, NaN pattern
+    identical), a sample matches the FP64 oracle, and the server's device
+    memory stays within BYTES_PER_SAMPLE per arena sample (plus staging-free
+    slack: the rings are host memory)."""
+    import paper_2604_06602_amd as umi
+    from paper_2604_06602_amd.serve import BYTES_PER_SAMPLE, NativeServer
+
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(40):
+        f, t, W = synth.curve_for(4, 100 + i)
+        L = min(f.size, 50000 if i % 9 == 0 else 20000)
+        iters = 3 if i % 2 else 5
+        tt = None if i % 5 == 3 else t[:L]
+        reqs.append((f[:L], tt, W, iters))
+    reqs.append((np.zeros(0, np.float32), None, 361, 5))
+    biggest = max(r[0].size for r in reqs)
+    capacity = max(biggest, sum(r[0].size for r in reqs) // 3)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    srv = NativeServer(capacity, max_curves=32, max_W=721, staging_bytes=32 << 20,
+                       max_step_samples=30000)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    print("native server test: %d requests, arena %d samples, %d bytes of device memory"
+          % (len(reqs), capacity, used), flush=True)
+    futs = [srv.submit(f, t, W, iters=it) for f, t, W, it in reqs]
+    results = [fu.result(timeout=120) for fu in futs]
+    summary = srv.summary()
+    srv.close()
+    assert used <= capacity * BYTES_PER_SAMPLE + 8 * (2 << 20), (used, capacity)
+    assert summary["completed"] == len(reqs) - 1 and summary["failed"] == 0
+    assert biggest > 30000  # at least one request is larger than a step
+    assert summary["largest_step_samples"] >= biggest  # it ran as a step of its own
+    for (f, t, W, it), res in zip(reqs, results):
+        assert res.shape == f.shape and res.dtype == np.float32
+        if f.size == 0:
+            continue
+        fd = torch.from_numpy(f).cuda()
+        td = None if t is None else torch.from_numpy(t).cuda()
+        alone, _ = umi.detrend(fd, td, W, iters=it)
+        torch.cuda.synchronize()
+        alone = alone.cpu().numpy()
+        assert np.array_equal(np.isnan(alone), np.isnan(res))
+        ok = ~np.isnan(res)
+        if ok.any():
+            rel = np.abs(alone[ok].astype(np.float64) - res[ok]) / np.abs(res[ok])
+            assert rel.max() <= 1e-5
+    for (f, t, W, it), res in list(zip(reqs, results))[:6]:
+        idx = np.unique(rng.integers(0, f.size, 40))
+        tt = np.zeros(f.size) if t is None else t
+        o_tr, _ = oracle_lib.detrend_at(f, tt, W, idx, iters=it)
+        ok = ~np.isnan(o_tr)
+        assert np.array_equal(np.isnan(res[idx]), ~ok)
+        rel = np.abs(res[idx][ok] - o_tr[ok]) / np.abs(o_tr[ok])
+        assert rel.max() <= 1e-5
