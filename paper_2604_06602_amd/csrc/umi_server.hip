@@ -657,11 +657,11 @@ struct umi_server {
     }
 
     // -- completion (waiter thread) -------------------------------------------
-    // The step's device work is done: copy every result into its request's
-    // output (on a copy pool of its own, so these copies never wait for the
-    // scheduler's staging copies), release the step's memory, report its
-    // completions.
-    void finish(Step* s)
+    // The step's device work is done (`device` is its completion event's
+    // status): copy every result into its request's output (on a copy pool of
+    // its own, so these copies never wait for the scheduler's staging copies),
+    // release the step's memory, report its completions.
+    void finish(Step* s, umi_status device)
     {
         const double t0 = umi::srv::now_s();
         std::vector<void*> d;
@@ -677,8 +677,10 @@ struct umi_server {
                 pos += r.n;
             }
         }
-        const umi_status cs = umi::host_copy_many(1, d.data(), src.data(), nb.data(),
-                                                  (int64_t)d.size(), cfg.copy_threads);
+        const umi_status cs =
+            device != UMI_OK ? device
+                             : umi::host_copy_many(1, d.data(), src.data(), nb.data(),
+                                                   (int64_t)d.size(), cfg.copy_threads);
         const double now = umi::srv::now_s();
         int64_t samples = 0, used;
         std::vector<umi_server_completion> done;
@@ -771,8 +773,8 @@ struct umi_server {
                 s = wait_q.front();
                 wait_q.pop_front();
             }
-            (void)hipEventSynchronize(s->done);
-            finish(s);
+            const hipError_t e = hipEventSynchronize(s->done);
+            finish(s, e == hipSuccess ? UMI_OK : UMI_ERR_DEVICE);
         }
     }
 
