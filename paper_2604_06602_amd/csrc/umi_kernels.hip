@@ -1386,6 +1386,95 @@ __device__ __forceinline__ void strided_sweep(const float* __restrict__ x, int l
     for (; j < n; j += G) f(x[j]);
 }
 
+// Sum over a group of G consecutive lanes (G = 2, 4, 8), integers.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    if (G >= 4) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if (G >= 8) v += (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    return v;
+}
+
+// Phase 1 of a split-tile window from the sorted tile alone (no wavelet
+// matrix), for tiles of at most kMainThreads staged samples.  The window's G
+// lanes walk the sorted (key, index) pairs from the smallest, 8G at a time
+// (lane l takes the 8 consecutive pairs from 8l), and count the pairs whose
+// compacted index lies in [ca, ca + n); the pair at which the count reaches
+// k + 1 is the window's k-th smallest, the same position wavelet_kth gives.
+// Each lane's counts of a step travel packed 4 bits per lane through one
+// group sum, so every lane of the group sees them all and takes the same
+// decisions.  Padding pairs (~0) lie in no window, and a step never reads
+// past npad (a power of two >= 64, so a multiple of 8G).  On a tile this
+// small the walk costs less than the wavelet build it replaces, whose
+// levels take four barriers each.  The median and n+ are the same integers
+// as window_phase1's.
+template <int G>
+__device__ __forceinline__ void window_phase1_scan(const MainSmem& sm, int nv, uint32_t ca,
+                                                   uint32_t n, float& m, uint32_t& nplus)
+{
+    const uint32_t l = threadIdx.x & (G - 1);
+    const uint32_t k = (n - 1) >> 1;
+    uint32_t need = k + 1;  // window pairs still to pass, the k-th included
+    uint32_t rk = 0;
+    for (int j0 = 0; j0 < nv; j0 += 8 * G) {
+        const int q0 = j0 + 8 * (int)l;
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = sm.sortbuf[q0 + u];
+        uint32_t bits = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            bits |= ((uint32_t)(v[u] & 0xffffffffull) - ca < n ? 1u : 0u) << u;
+        const uint32_t packed = group_sum_u32<G>((uint32_t)__popc(bits) << (4 * l));
+        uint32_t below = 0, lane_hit = G;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t cg = (packed >> (4 * g)) & 15u;
+            if (lane_hit == G) {
+                if (below + cg >= need)
+                    lane_hit = g;
+                else
+                    below += cg;
+            }
+        }
+        if (lane_hit == G) {  // not in this step
+            need -= below;
+            continue;
+        }
+        // the (need - below)-th window pair of lane lane_hit's eight
+        uint32_t pos = 0;
+        if (l == lane_hit) {
+            uint32_t b = bits;
+            for (uint32_t r = need - below; r > 1u; --r) b &= b - 1u;
+            pos = (uint32_t)q0 + (uint32_t)__builtin_ctz(b);
+        }
+        rk = group_sum_u32<G>(pos);
+        break;
+    }
+    m = key_value((uint32_t)(sm.sortbuf[rk] >> 32));
+    // the points strictly above m: the window pairs after the last tile pair
+    // numerically equal to m (ties sit next to m in the sorted order)
+    uint32_t rh = rk, hi = rk + 1, step = 1;
+    while (hi < (uint32_t)nv && key_value((uint32_t)(sm.sortbuf[hi] >> 32)) == m) {
+        rh = hi;
+        hi = rh + (step <<= 1);
+    }
+    if (hi > (uint32_t)nv) hi = (uint32_t)nv;
+    while (hi - rh > 1u) {  // last equal in [rh, hi)
+        const uint32_t mid = (rh + hi) >> 1;
+        if (key_value((uint32_t)(sm.sortbuf[mid] >> 32)) == m)
+            rh = mid;
+        else
+            hi = mid;
+    }
+    uint32_t tied = 0;
+    for (uint32_t j = rk + 1 + l; j <= rh; j += G)
+        tied += ((uint32_t)(sm.sortbuf[j] & 0xffffffffull) - ca < n) ? 1u : 0u;
+    tied = group_sum_u32<G>(tied);
+    nplus = n - k - 1 - tied;
+}
+
 template <int G, int kFeat>
 __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int levels, int nv,
                                                    const CurveDesc& cd, int h, int s0, int N,
@@ -1395,7 +1484,7 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
                                                    const double* __restrict__ time,
                                                    float* __restrict__ trend,
                                                    float* __restrict__ median,
-                                                   float* __restrict__ detrended)
+                                                   float* __restrict__ detrended, bool scan)
 {
     const int m_min = max(1, cd.W / 3);
     const int l = (int)threadIdx.x & (G - 1);
@@ -1405,7 +1494,12 @@ __device__ __forceinline__ void tile_windows_split(const MainSmem& sm, int level
         p < t1 && window_range<kFeat>(sm, cd, segid, time, h, s0, N, m_min, p, ca, n);
     float m = 0.0f, sc = 0.0f;
     uint32_t nplus = 0;
-    if (live) window_phase1(sm, levels, nv, scale, ca, n, m, sc, nplus);  // same on every lane
+    if (live) {  // same on every lane
+        if (scan)
+            window_phase1_scan<G>(sm, nv, ca, n, m, nplus);
+        else
+            window_phase1(sm, levels, nv, scale, ca, n, m, sc, nplus);
+    }
     const float* x = sm.xv + ca;
     if (live && scale != UMI_SCALE_MAD) {
         // Phase 2 (Eq. 1)
@@ -1532,6 +1626,8 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         while (npad < nv) npad <<= 1;
         int levels = 6;
         while ((1 << levels) < npad) ++levels;
+        const bool scan_tile = (kFeat & kFeatSplit) && G > 1 && npad <= kMainThreads &&
+                               scale != UMI_SCALE_MAD;
 
         if (simple) {
             // every staged sample is valid: values and keys in index order
@@ -1597,7 +1693,9 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
         }
 
-        // --- wavelet matrix over the sequence rank_of[compacted index] ---
+        // --- wavelet matrix over the sequence rank_of[compacted index]; small
+        // split tiles take their medians from the sorted tile directly ---
+        if (!scan_tile) {
         for (int r = tid; r < npad; r += kMainThreads) {
             if (r < nv)
                 sm.seq[0][(uint32_t)(sm.sortbuf[r] & 0xffffffffull)] = (uint16_t)r;
@@ -1634,6 +1732,7 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
             __syncthreads();
         }
+        }  // wavelet
         }  // not simple
 
         // --- the tile's windows: G lanes per position, or R consecutive
@@ -1641,13 +1740,13 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         if ((kFeat & kFeatSplit) && G > 1) {
             if (G == 2)
                 tile_windows_split<2, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
-                                      scale, time, trend, median, detrended);
+                                      scale, time, trend, median, detrended, scan_tile);
             else if (G == 4)
                 tile_windows_split<4, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
-                                      scale, time, trend, median, detrended);
+                                      scale, time, trend, median, detrended, scan_tile);
             else
                 tile_windows_split<8, kFeat>(sm, levels, nv, cd, h, s0, N, t0, t1, segid, alpha, c, iters,
-                                      scale, time, trend, median, detrended);
+                                      scale, time, trend, median, detrended, scan_tile);
             __syncthreads();
             continue;
         }
