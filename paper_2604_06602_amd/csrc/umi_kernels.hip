@@ -1397,18 +1397,17 @@ __device__ __forceinline__ uint32_t group_sum_u32(uint32_t v)
 }
 
 // Phase 1 of a split-tile window from the sorted tile alone (no wavelet
-// matrix), for tiles of at most kMainThreads staged samples.  The window's G
-// lanes walk the sorted (key, index) pairs from the smallest, 8G at a time
-// (lane l takes the 8 consecutive pairs from 8l), and count the pairs whose
-// compacted index lies in [ca, ca + n); the pair at which the count reaches
-// k + 1 is the window's k-th smallest, the same position wavelet_kth gives.
-// Each lane's counts of a step travel packed 4 bits per lane through one
-// group sum, so every lane of the group sees them all and takes the same
-// decisions.  Padding pairs (~0) lie in no window, and a step never reads
-// past npad (a power of two >= 64, so a multiple of 8G).  On a tile this
-// small the walk costs less than the wavelet build it replaces, whose
-// levels take four barriers each.  The median and n+ are the same integers
-// as window_phase1's.
+// matrix).  The window's G lanes walk the sorted (key, index) pairs from the
+// smallest, 8G at a time (lane l takes the 8 consecutive pairs from 8l), and
+// count the pairs whose compacted index lies in [ca, ca + n); the pair at
+// which the count reaches k + 1 is the window's k-th smallest, the same
+// position wavelet_kth gives.  Each lane's counts of a step travel packed 4
+// bits per lane through one group sum, so every lane of the group sees them
+// all and takes the same decisions.  Padding pairs (~0) lie in no window, and
+// a step never reads past npad (a power of two >= 64, so a multiple of 8G).
+// The walk takes about nv / 16G steps to a median, against a wavelet build
+// of log2(npad) levels of four barriers each for the whole tile.  The median
+// and n+ are the same integers as window_phase1's.
 template <int G>
 __device__ __forceinline__ void window_phase1_scan(const MainSmem& sm, int nv, uint32_t ca,
                                                    uint32_t n, float& m, uint32_t& nplus)
@@ -1626,8 +1625,7 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
         while (npad < nv) npad <<= 1;
         int levels = 6;
         while ((1 << levels) < npad) ++levels;
-        const bool scan_tile = (kFeat & kFeatSplit) && G > 1 && npad <= kMainThreads &&
-                               scale != UMI_SCALE_MAD;
+        const bool scan_tile = (kFeat & kFeatSplit) && G > 1 && scale != UMI_SCALE_MAD;
 
         if (simple) {
             // every staged sample is valid: values and keys in index order
@@ -1693,8 +1691,8 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
             }
         }
 
-        // --- wavelet matrix over the sequence rank_of[compacted index]; small
-        // split tiles take their medians from the sorted tile directly ---
+        // --- wavelet matrix over the sequence rank_of[compacted index]; split
+        // tiles take their medians from the sorted tile directly ---
         if (!scan_tile) {
         for (int r = tid; r < npad; r += kMainThreads) {
             if (r < nv)
