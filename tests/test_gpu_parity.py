@@ -367,3 +367,33 @@ def test_lone_curve_takes_split_tiles(torch, umi, oracle_lib):
     assert np.array_equal(auto[0].view(np.uint32), forced[0].view(np.uint32))
     o_tr, o_md = oracle_lib.detrend(flux, time, W)
     assert_parity(auto[0], auto[1], o_tr, o_md, what="lone curve, library tiles")
+
+
+@pytest.mark.parametrize("tile", [256, 128, 64])
+def test_split_walk_at_large_windows_with_ties(torch, umi, oracle_lib, tile):
+    """Split tiles take each window's median by walking the sorted tile: at
+    W = 721, 1441 and 2047 (staged spans of up to 2,048 samples) on flux
+    rounded into long runs of ties, with and without NaN gaps, the medians
+    equal those of 1536-position launches bit for bit (one lane per window
+    and the wavelet matrix, except at W = 2047, whose tiles hold at most two
+    positions and split at any size), and both match the oracle."""
+    rng = np.random.default_rng(31)
+    dt = 2 / 1440
+    curves = []
+    for W in (721, 1441, 2047):
+        f = np.round(rng.normal(1, 1e-3, 6000), 3).astype(np.float32)
+        curves.append((f, np.arange(6000) * dt, W))
+        g = np.round(rng.normal(1, 1e-3, 5000), 4).astype(np.float32)
+        g[rng.random(5000) < 0.1] = np.nan
+        g[2000:2600] = np.nan
+        curves.append((g, np.arange(5000) * dt, W))
+    b = synth.lightcurves.pack(curves)
+    o_tr, o_md = oracle_lib.detrend_batch(b.flux, b.time, b.lengths, b.W)
+    mag = window_magnitude(b.flux, b.time, b.lengths, b.W, oracle_lib)
+    one = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W,
+                    launch=umi.LaunchOptions(tile=1536))
+    split = run_batch(torch, umi, b.flux, b.time, b.lengths, b.W,
+                      launch=umi.LaunchOptions(tile=tile))
+    assert np.array_equal(split[1].view(np.uint32), one[1].view(np.uint32))
+    assert_parity(split[0], split[1], o_tr, o_md, scale=mag, what="walk tile %d" % tile)
+    assert_parity(one[0], one[1], o_tr, o_md, scale=mag, what="one lane")
