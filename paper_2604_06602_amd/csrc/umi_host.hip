@@ -1340,7 +1340,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.8.2"; }
+const char* umi_version(void) { return "umi-mi355x 0.8.3"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

@@ -105,7 +105,7 @@ struct Counters {
     uint32_t queue;     // estimate-kernel tile queue (cleared by the pre-pass)
     uint32_t tickets;   // pre-pass chunk tickets (reset by its last workgroup)
     uint32_t done;      // pre-pass workgroups finished (reset likewise)
-    uint32_t reserved;
+    uint32_t trash;     // takes the walker pre-pass's stores that have no sample
     uint64_t epoch;     // pre-pass launches completed; stamps use epoch + 1
     uint64_t reserved2;
 };

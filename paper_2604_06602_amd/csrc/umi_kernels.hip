@@ -563,15 +563,17 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
 // the curve's chunks of NT * K samples in order and carries the scan state in
 // registers (the next chunk's loads are issued before the current chunk's
 // scans).  No tickets, records or look-back: batches of many curves fill the
-// chip this way, and every chunk costs one pass.  Two barriers per chunk:
+// chip this way, and every chunk costs one pass.  kTime: a time array is
+// given (without one nothing breaks a segment).  Two barriers per chunk:
 // each LDS array is written in one phase and read in the next, and a phase's
 // writes follow the barrier that ends every wave's reads of the same array in
 // the chunk before.
-template <int NT, int K>
+template <int NT, int K, bool kTime>
 __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
     const uint8_t* __restrict__ block, uint8_t* __restrict__ block_to, int curve_first,
-    int32_t* __restrict__ segid, int2* __restrict__ tiles, uint32_t* __restrict__ counter)
+    int32_t* __restrict__ segid, int2* __restrict__ tiles, uint32_t* __restrict__ counter,
+    int32_t* __restrict__ trash)
 {
     const BatchHeader* __restrict__ hdr = reinterpret_cast<const BatchHeader*>(block);
     const CurveDesc* __restrict__ curves =
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
         tiles[cd.tile_base + t] = make_int2(cidx, t * cd.tile);
 
     const float* f = flux + cd.off;
-    const double* tm = time ? time + cd.off : nullptr;
+    const double* tm = time + (kTime ? cd.off : 0);  // unused without times
     int32_t* sid = segid + cd.off;
 
     // carries from earlier chunks (uniform over the block)
@@ -610,30 +612,35 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
     constexpr int kChunk = NT * K;
 
     // The next chunk's flux and times are loaded while the current one is
-    // scanned, so the loads' latency overlaps the scans.
+    // scanned, so the loads' latency overlaps the scans.  Every step issues
+    // the same loads and stores whatever the data (indices past the curve
+    // load its last sample and store to `trash`), so the wait for a chunk's
+    // loads counts only the memory operations issued after them and never
+    // waits for the previous chunk's stores or the next chunk's loads.
+    const int last = cd.len - 1;
     float fv[K];
     double tv[K];
     auto load_chunk = [&](int base, float* fo, double* to) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const int e = base + (int)threadIdx.x * K + q;
-            fo[q] = e < cd.len ? f[e] : __builtin_nanf("");
-            to[q] = (tm != nullptr && e < cd.len) ? tm[e] : 0.0;
+            const int e = min(base + (int)threadIdx.x * K + q, last);
+            fo[q] = f[e];
+            to[q] = kTime ? tm[e] : 0.0;
         }
     };
-    load_chunk(0, fv, tv);
+    if (cd.len > 0) load_chunk(0, fv, tv);
 
     for (int base = 0; base < cd.len; base += kChunk) {
         float nf[K];
         double nt[K];
-        if (base + kChunk < cd.len) load_chunk(base + kChunk, nf, nt);
+        load_chunk(base + kChunk, nf, nt);
         const int e0 = base + (int)threadIdx.x * K;
         uint32_t vmask = 0;  // bit q: item q is valid
         int vi = -1, vc = 0;
         double vt = 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const bool ok = e0 + q < cd.len && isfinite(fv[q]) && (tm == nullptr || isfinite(tv[q]));
+            const bool ok = e0 + q < cd.len && isfinite(fv[q]) && (!kTime || isfinite(tv[q]));
             vmask |= (ok ? 1u : 0u) << q;
             if (ok) {
                 vi = e0 + q;
@@ -681,7 +688,7 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 if ((vmask >> q) & 1u) {
-                    if (pi < 0 || (tm != nullptr && (tv[q] - pt) > kGapDays)) {
+                    if (pi < 0 || (kTime && (tv[q] - pt) > kGapDays)) {
                         sx = e0 + q;
                         sz = v;
                     }
@@ -722,7 +729,8 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
             c_sz = bz;
         }
 
-        // writes: segment of each item; a start closes the segment before it
+        // writes: segment of each item; a start closes the segment before it.
+        // One store per item, its address and value chosen by selects.
         {
             int pi = ex_i;
             double pt = ex_t;
@@ -730,21 +738,19 @@ __global__ __launch_bounds__(NT) void umi_prepass_walk_kernel(
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 const int e = e0 + q;
-                if (e < cd.len) {
-                    if ((vmask >> q) & 1u) {
-                        if (pi < 0 || (tm != nullptr && (tv[q] - pt) > kGapDays)) {
-                            if (px >= 0) sid[px] = -2 - (v - pz);
-                            px = e;
-                            pz = v;
-                        } else {
-                            sid[e] = px;
-                        }
-                        pi = e;
-                        pt = tv[q];
-                        ++v;
-                    } else {
-                        sid[e] = -1;
-                    }
+                const bool valid = (vmask >> q) & 1u;  // implies e < cd.len
+                const bool start = valid && (pi < 0 || (kTime && (tv[q] - pt) > kGapDays));
+                int32_t* dst = start ? (px >= 0 ? sid + px : trash) : (e < cd.len ? sid + e : trash);
+                const int32_t val = start ? -2 - (v - pz) : (valid ? px : -1);
+                *dst = val;
+                if (start) {
+                    px = e;
+                    pz = v;
+                }
+                if (valid) {
+                    pi = e;
+                    pt = tv[q];
+                    ++v;
                 }
             }
         }
@@ -1827,11 +1833,18 @@ hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
     // `block`), or from `block` itself
     const uint8_t* src = stage ? stage : block;
     uint8_t* to = stage ? block : nullptr;
-    if (walk)  // one workgroup per curve, from curve_one (or the first) on
-        hipLaunchKernelGGL((umi_prepass_walk_kernel<kPrepThreads, kPrepWalkItems>), dim3(grid),
-                           dim3(kPrepThreads), 0, stream, flux, time, src, to,
+    // one workgroup per curve, from curve_one (or the first) on
+    int32_t* trash = reinterpret_cast<int32_t*>(&ctr->trash);
+    if (walk && time)
+        hipLaunchKernelGGL((umi_prepass_walk_kernel<kPrepThreads, kPrepWalkItems, true>),
+                           dim3(grid), dim3(kPrepThreads), 0, stream, flux, time, src, to,
                            curve_one < 0 ? 0 : curve_one, segid, tiles,
-                           clear_queue ? &ctr->queue : nullptr);
+                           clear_queue ? &ctr->queue : nullptr, trash);
+    else if (walk)
+        hipLaunchKernelGGL((umi_prepass_walk_kernel<kPrepThreads, kPrepWalkItems, false>),
+                           dim3(grid), dim3(kPrepThreads), 0, stream, flux, time, src, to,
+                           curve_one < 0 ? 0 : curve_one, segid, tiles,
+                           clear_queue ? &ctr->queue : nullptr, trash);
     else
         hipLaunchKernelGGL((umi_prepass_chunk_kernel<kPrepThreads, kPrepItems>), dim3(grid),
                            dim3(kPrepThreads), 0, stream, flux, time, src, to, curve_one,
