@@ -397,3 +397,30 @@ def test_split_walk_at_large_windows_with_ties(torch, umi, oracle_lib, tile):
     assert np.array_equal(split[1].view(np.uint32), one[1].view(np.uint32))
     assert_parity(split[0], split[1], o_tr, o_md, scale=mag, what="walk tile %d" % tile)
     assert_parity(one[0], one[1], o_tr, o_md, scale=mag, what="one lane")
+
+
+def test_walker_without_time_array(torch, umi, oracle_lib):
+    """A batch of 150 curves takes the one-workgroup-per-curve pre-pass; with
+    no time array (nothing breaks a segment) it runs that pre-pass's
+    instance without times.  Persistent and per-curve launches give the
+    same bits, and both match the oracle, with NaN runs, isolated NaNs,
+    curves shorter than W and curves spanning several pre-pass chunks."""
+    rng = np.random.default_rng(41)
+    lengths = rng.integers(50, 3000, 150)
+    lengths[:3] = [1, 2, 1025]
+    parts = []
+    for L in lengths:
+        f = rng.normal(1, 1e-3, int(L)).astype(np.float32)
+        f[rng.random(int(L)) < 0.05] = np.nan
+        if L > 600:
+            f[200:500] = np.nan
+        parts.append(f)
+    flux = np.concatenate(parts)
+    W = [121] * 150
+    o_tr, o_md = oracle_lib.detrend_batch(flux, None, lengths, W)
+    per = run_batch(torch, umi, flux, None, lengths, W,
+                    launch=umi.LaunchOptions(mode=umi.MODE_PER_CURVE))
+    pers = run_batch(torch, umi, flux, None, lengths, W)
+    assert np.array_equal(per[0].view(np.uint32), pers[0].view(np.uint32))
+    assert np.array_equal(per[1].view(np.uint32), pers[1].view(np.uint32))
+    assert_parity(pers[0], pers[1], o_tr, o_md, what="walker without times")
