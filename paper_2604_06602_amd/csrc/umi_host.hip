@@ -29,7 +29,7 @@ namespace umi {
 hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
                           const uint8_t* stage, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
-                          hipStream_t stream);
+                          const CurveDesc* one, hipStream_t stream);
 hipError_t launch_copy(const CopyBatch& cb, hipStream_t stream);
 hipError_t launch_main(const float* flux, const int32_t* segid, const BatchHeader* hdr,
                        const CurveDesc* curves, const int2* tiles, int tile_first,
@@ -471,8 +471,10 @@ hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, 
     const CurveDesc* curves = reinterpret_cast<const CurveDesc*>(dblock + sizeof(BatchHeader));
     hipError_t e;
     if (mode == UMI_MODE_PERSISTENT) {
+        // a lone curve's descriptor goes to the chunked pre-pass as an argument
+        const CurveDesc* one = (table != nullptr && ncurves == 1 && !prep.walk) ? table : nullptr;
         if ((e = launch_prepass(flux, time, dblock, stage, -1, prep.grid, b.segid, b.tiles, b.ctr,
-                                b.recs, true, prep.walk, stream)) != hipSuccess)
+                                b.recs, true, prep.walk, one, stream)) != hipSuccess)
             return e;
         if (staged && (e = hipEventRecord(staged, stream)) != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
@@ -487,7 +489,7 @@ hipError_t enqueue_kernels(const float* flux, const double* time, float* trend, 
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return e;
     for (int i = 0; i < ncurves; ++i) {
         if ((e = launch_prepass(flux, time, dblock, nullptr, i, 1, b.segid, b.tiles, b.ctr,
-                                b.recs, false, true, stream)) != hipSuccess)
+                                b.recs, false, true, nullptr, stream)) != hipSuccess)
             return e;
         const int nt = (int)curve_tiles[i];
         if ((e = launch_main(flux, b.segid, hdr, curves, b.tiles, table[i].tile_base, nt, nullptr,
@@ -1340,7 +1342,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.8.3"; }
+const char* umi_version(void) { return "umi-mi355x 0.8.4"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
     const float* __restrict__ flux, const double* __restrict__ time,
     const uint8_t* __restrict__ block, uint8_t* __restrict__ block_to, int curve_one,
     int32_t* __restrict__ segid, int2* __restrict__ tiles, Counters* __restrict__ ctr,
-    ChunkRec* __restrict__ recs, int clear_queue)
+    ChunkRec* __restrict__ recs, int clear_queue, CurveDesc one, int one_chunks)
 {
     const BatchHeader* __restrict__ hdr = reinterpret_cast<const BatchHeader*>(block);
     const CurveDesc* __restrict__ curves =
@@ -326,11 +326,14 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
     if (clear_queue && blockIdx.x == 0 && tid == 0) ctr->queue = 0u;
     const uint64_t epoch_word = ctr->epoch;
     const uint32_t stamp = (uint32_t)(epoch_word + 1);  // this launch's record stamp
-    // one curve (per-curve launches) or the whole batch
-    const int n_chunks = curve_one >= 0
-                             ? (curves[curve_one].len + kChunk - 1) / kChunk
-                             : hdr->n_chunks;
-    const int n_curves = hdr->n_curves;
+    // one curve (per-curve launches) or the whole batch; a batch of one curve
+    // may come with its descriptor and chunk count as arguments, so that no
+    // step waits on a read of the table over the bus
+    const bool given = one_chunks >= 0;
+    const int n_chunks = given ? one_chunks
+                               : (curve_one >= 0 ? (curves[curve_one].len + kChunk - 1) / kChunk
+                                                 : hdr->n_chunks);
+    const int n_curves = given ? 1 : hdr->n_curves;
     stage_block_copy(block, block_to, n_curves, NT);
 
     for (;;) {
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(NT) void umi_prepass_chunk_kernel(
         }
         __syncthreads();
         const int cidx = sh_curve;
-        const CurveDesc cd = curves[cidx];
+        const CurveDesc cd = given ? one : curves[cidx];
         const int g0 = curve_one >= 0 ? 0 : cd.chunk_base;  // the curve's first chunk
         const int lo = (g - g0) * kChunk;
         const int hi = min(lo + kChunk, cd.len);
@@ -1823,10 +1826,13 @@ __global__ __launch_bounds__(256) void umi_copy_kernel(CopyBatch cb)
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers (the host library calls only these).
 
+// `one` (host memory, read before the call returns), for a batch of one curve
+// taking the chunked form: that curve's table entry, passed to the kernel by
+// value so that it need not read the staged table before its first step.
 hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
                           const uint8_t* stage, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
-                          hipStream_t stream)
+                          const CurveDesc* one, hipStream_t stream)
 {
     if (grid <= 0) return hipSuccess;
     // read the header and table from the staging block (and copy them into
@@ -1848,7 +1854,9 @@ hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
     else
         hipLaunchKernelGGL((umi_prepass_chunk_kernel<kPrepThreads, kPrepItems>), dim3(grid),
                            dim3(kPrepThreads), 0, stream, flux, time, src, to, curve_one,
-                           segid, tiles, ctr, recs, clear_queue ? 1 : 0);
+                           segid, tiles, ctr, recs, clear_queue ? 1 : 0,
+                           one ? *one : CurveDesc{},
+                           one ? (one->len + kPrepChunk - 1) / kPrepChunk : -1);
     return hipGetLastError();
 }
 

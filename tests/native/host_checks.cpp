@@ -116,9 +116,16 @@ hipError_t prepass_now(const float* flux, const double* time, uint8_t* block,
 hipError_t launch_prepass(const float* flux, const double* time, uint8_t* block,
                           const uint8_t* stage, int curve_one, int grid, int32_t* segid,
                           int2* tiles, Counters* ctr, ChunkRec* recs, bool clear_queue, bool walk,
-                          hipStream_t)
+                          const CurveDesc* one, hipStream_t)
 {
     if (curve_one >= 0) CHECK(stage == nullptr);  // per-curve launches copy the block first
+    if (one != nullptr) {
+        // a lone curve's entry, for the chunked form, equal to the staged one
+        CHECK(curve_one < 0 && !walk);
+        const uint8_t* src = stage ? stage : block;
+        CHECK(reinterpret_cast<const BatchHeader*>(src)->n_curves == 1);
+        CHECK(std::memcmp(one, src + sizeof(BatchHeader), sizeof(CurveDesc)) == 0);
+    }
     return fake_hip::record_or_run([=] {
         return prepass_now(flux, time, block, stage, curve_one, grid, segid, tiles, ctr, recs,
                            clear_queue, walk);
