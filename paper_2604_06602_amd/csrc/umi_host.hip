@@ -1342,7 +1342,7 @@ void umi_release(void)
     umi::g_ws.clear();
 }
 
-const char* umi_version(void) { return "umi-mi355x 0.8.4"; }
+const char* umi_version(void) { return "umi-mi355x 0.8.5"; }
 
 void umi_debug_inject_error(umi_status s) { umi::t_inject = s; }
 

@@ -1573,9 +1573,20 @@ __global__ __launch_bounds__(kMainThreads, 8) void umi_main_kernel(
     const int tile_end = tile_count < 0 ? hdr->n_tiles : tile_first + tile_count;
 
     for (int round = 0;; ++round) {
-        if (tid == 0)
-            sm.tile = counter ? tile_first + (int)atomicAdd(counter, 1u)
-                              : tile_first + (int)blockIdx.x + round * (int)gridDim.x;
+        // Instances with split tiles serve small batches, where a workgroup
+        // often has one tile: its first tile is its block index, and the
+        // queue counter hands out the tiles after the grid's first round
+        // (not touched at all when the first round covers every tile).
+        constexpr bool kStaticFirst = (kFeat & kFeatSplit) != 0;
+        if (tid == 0) {
+            if (counter && !(kStaticFirst && round == 0))
+                sm.tile = (kStaticFirst && tile_first + (int)gridDim.x >= tile_end)
+                              ? tile_end
+                              : tile_first + (kStaticFirst ? (int)gridDim.x : 0) +
+                                    (int)atomicAdd(counter, 1u);
+            else
+                sm.tile = tile_first + (int)blockIdx.x + round * (int)gridDim.x;
+        }
         __syncthreads();
         const int tile = sm.tile;
         if (tile >= tile_end) break;
